@@ -1,0 +1,330 @@
+// Device kernels of libvlp: key preparation, batched blind rotation with
+// sample extraction, batched key switching, and small helpers.
+#include <hip/hip_runtime.h>
+
+#include "gl64.h"
+#include "internal.h"
+#include "wave_ntt.h"
+
+namespace vlp {
+
+// ---------------------------------------------------------------------------
+// Key preparation
+// ---------------------------------------------------------------------------
+
+// One wave per bootstrapping-key polynomial: residues of the coefficient words
+// (taken as integers in [0, 2^32)), forward transform, times 1/1024.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t* __restrict__ bk_coeff,
+                                                                   uint64_t* __restrict__ bk_ntt,
+                                                                   const uint64_t* __restrict__ tw_fwd,
+                                                                   uint32_t n_polys, uint64_t n_inv) {
+  __shared__ uint64_t s_tw[RING_N];
+  __shared__ uint64_t s_buf[WAVES][RING_N];
+  for (int k = threadIdx.x; k < RING_N; k += blockDim.x) s_tw[k] = tw_fwd[k];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (uint32_t poly = blockIdx.x * WAVES + wave; poly < n_polys; poly += gridDim.x * WAVES) {
+    const uint32_t* src = bk_coeff + (size_t)poly * RING_N;
+    uint64_t v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = src[lay_a(lane, r)];
+    ntt_fwd(v, s_buf[wave], s_tw, lane);
+    uint64_t* dst = bk_ntt + (size_t)poly * RING_N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dst[r * 64 + lane] = gl_canon(gl_mul(v[r], n_inv));
+  }
+}
+
+// ksk_out[i][j][v-1][w] = ksk_in[i][j][v][w] for v = 1..3, w < 631; pad words are 0.
+__global__ void ksk_relayout_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out) {
+  const size_t total = KSK_WORDS;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t w = (uint32_t)(idx % KS_ROW);
+    const size_t row = idx / KS_ROW;            // (i*8 + j)*3 + (v-1)
+    const size_t ij = row / 3, v = row % 3 + 1;
+    out[idx] = w < (uint32_t)CT_n ? in[(ij * 4 + v) * CT_n + w] : 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blind rotation + sample extraction, one wavefront per item.
+// ---------------------------------------------------------------------------
+constexpr uint32_t DEC_OFFSET = (1u << 31) + (1u << 24) + (1u << 17) + (1u << 10);
+
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict__ items, uint32_t count,
+                                                         const uint64_t* __restrict__ tw_fwd,
+                                                         const uint64_t* __restrict__ tw_inv) {
+  __shared__ uint64_t s_tw[2][RING_N];            // forward / inverse twiddles
+  __shared__ uint64_t s_buf[WAVES][RING_N];       // transpose scratch, one per wave
+  __shared__ uint32_t s_acc[WAVES][2][RING_N];    // accumulator (A, B), coefficient order
+  __shared__ uint16_t s_abar[WAVES][CT_n + 1];    // modulus-switched input
+  for (int k = threadIdx.x; k < RING_N; k += blockDim.x) {
+    s_tw[0][k] = tw_fwd[k];
+    s_tw[1][k] = tw_inv[k];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint64_t* buf = s_buf[wave];
+  uint32_t* acc = s_acc[wave][0];
+  uint16_t* abar = s_abar[wave];
+
+  for (uint32_t it = blockIdx.x * WAVES + wave; it < count; it += gridDim.x * WAVES) {
+    const BrItem I = items[it];
+    // Gate pre-combination and modulus switch of all 631 words.
+    wave_lds_sync();
+    for (int w = lane; w < CT_n; w += 64) {
+      uint32_t x = (uint32_t)I.ca * I.a[w];
+      if (I.b) x += (uint32_t)I.cb * I.b[w];
+      if (w == LWE_n) x += I.cst;
+      abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
+    }
+    wave_lds_sync();
+    // acc = (0, X^(-bbar) * mu * (1 + X + ... + X^1023)).
+    const uint32_t bbar = __builtin_amdgcn_readfirstlane(abar[LWE_n]);
+    const uint32_t rot = (2048u - bbar) & 2047u;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t j = r * 64 + lane;
+      const bool neg = (j < (rot & 1023u)) != (rot >= 1024u);
+      acc[j] = 0;
+      acc[RING_N + j] = neg ? (0u - I.mu) : I.mu;
+    }
+    const uint64_t* bk_i = I.bk;
+    for (int i = 0; i < LWE_n; ++i, bk_i += 2 * ELL * 2 * RING_N) {
+      const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
+      if (ab == 0) continue;
+      wave_lds_sync();  // accumulator updates of the previous step are visible
+      // External product BK_i x (X^ab acc - acc), accumulated in the transform domain.
+      uint64_t acc0[16], acc1[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
+#pragma unroll 1
+      for (int row = 0; row < 2 * ELL; ++row) {
+        const int c = row < ELL ? 0 : 1;
+        const int lev = row - c * ELL;
+        const int shift = 32 - BG_BIT * (lev + 1);
+        const uint32_t* poly = acc + c * RING_N;
+        uint64_t v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const uint32_t j = r * 64 + lane;
+          const uint32_t s = (j + 2048u - ab) & 2047u;  // X^ab: coefficient j comes from j - ab
+          const uint32_t src = poly[s & 1023u];
+          const uint32_t dj = (s >= 1024u ? 0u - src : src) - poly[j];
+          const int32_t d = (int32_t)(((dj + DEC_OFFSET) >> shift) & 127u) - 64;
+          v[r] = gl_from_i32(d);
+        }
+        ntt_fwd(v, buf, s_tw[0], lane);
+        const uint64_t* k0 = bk_i + (size_t)(row * 2) * RING_N;
+        const uint64_t* k1 = k0 + RING_N;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          acc0[r] = gl_add_wc(acc0[r], gl_canon(gl_mul(v[r], k0[r * 64 + lane])));
+          acc1[r] = gl_add_wc(acc1[r], gl_canon(gl_mul(v[r], k1[r * 64 + lane])));
+        }
+      }
+#pragma unroll 1
+      for (int c = 0; c < 2; ++c) {
+        uint64_t v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = c ? acc1[r] : acc0[r];
+        ntt_inv(v, buf, s_tw[1], lane);
+        uint32_t* poly = acc + c * RING_N;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) poly[r * 64 + lane] += gl_lift_u32(v[r]);
+      }
+    }
+    wave_lds_sync();
+    // SampleExtract: a'_0 = A_0, a'_j = -A_(N-j), b' = B_0.
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int j = r * 64 + lane;
+      const uint32_t a = acc[j];
+      if (j == 0) I.out[0] = a;
+      else I.out[RING_N - j] = 0u - a;
+    }
+    if (lane == 0) I.out[RING_N] = acc[RING_N];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Key switching: a block handles T gates that share one key; each of the
+// block's 320 threads owns two of the 640 padded output words.
+// ---------------------------------------------------------------------------
+constexpr int KS_THREADS = 320;
+
+template <int T>
+__global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict__ items, uint32_t count,
+                                                         const uint32_t* __restrict__ ksk) {
+  __shared__ uint32_t s_a[T][RING_N];
+  const uint32_t base = blockIdx.x * T;
+  const int nt = (int)min((uint32_t)T, count - base);
+  for (int idx = threadIdx.x; idx < T * RING_N; idx += KS_THREADS) {
+    const int g = idx / RING_N, i = idx % RING_N;
+    uint32_t a = 0;
+    if (g < nt) {
+      const KsItem& it = items[base + g];
+      a = it.u1[i] + (it.u2 ? it.u2[i] : 0u);
+    }
+    s_a[g][i] = a + (1u << 15);  // rounding offset of the key-switching digits
+  }
+  const int w0 = threadIdx.x, w1 = threadIdx.x + KS_THREADS;
+  uint32_t acc[T][2];
+#pragma unroll
+  for (int g = 0; g < T; ++g) {
+    uint32_t body = 0;
+    if (g < nt && w1 == LWE_n) {  // the body word sits in the second half (320 <= 630 < 640)
+      const KsItem& it = items[base + g];
+      body = it.u1[RING_N] + (it.u2 ? it.u2[RING_N] : 0u) + it.cst;
+    }
+    acc[g][0] = 0;
+    acc[g][1] = body;
+  }
+  __syncthreads();
+  for (int i = 0; i < RING_N; ++i) {
+    uint32_t a[T];
+#pragma unroll
+    for (int g = 0; g < T; ++g) a[g] = s_a[g][i];
+#pragma unroll 2
+    for (int j = 0; j < KS_T; ++j) {
+      const uint32_t* row = ksk + (size_t)((i * KS_T + j) * 3) * KS_ROW;
+      const uint32_t k10 = row[w0], k11 = row[w1];
+      const uint32_t k20 = row[KS_ROW + w0], k21 = row[KS_ROW + w1];
+      const uint32_t k30 = row[2 * KS_ROW + w0], k31 = row[2 * KS_ROW + w1];
+      const int sh = 30 - 2 * j;
+#pragma unroll
+      for (int g = 0; g < T; ++g) {
+        const uint32_t d = (a[g] >> sh) & 3u;
+        const uint32_t s0 = d == 0 ? 0u : (d == 1 ? k10 : (d == 2 ? k20 : k30));
+        const uint32_t s1 = d == 0 ? 0u : (d == 1 ? k11 : (d == 2 ? k21 : k31));
+        acc[g][0] -= s0;
+        acc[g][1] -= s1;
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < T; ++g) {
+    if (g < nt) {
+      uint32_t* out = items[base + g].out;
+      if (w0 < CT_n) out[w0] = acc[g][0];
+      if (w1 < CT_n) out[w1] = acc[g][1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Helpers
+// ---------------------------------------------------------------------------
+__global__ void make_br_items_kernel(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca,
+                                     int32_t cb, uint32_t cst, uint32_t mu, uint32_t* out, const uint64_t* bk) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  BrItem it;
+  it.a = a + (size_t)t * CT_n;
+  it.b = b ? b + (size_t)t * CT_n : nullptr;
+  it.out = out + (size_t)t * CT_N;
+  it.bk = bk;
+  it.ca = ca;
+  it.cb = cb;
+  it.cst = cst;
+  it.mu = mu;
+  items[t] = it;
+}
+
+__global__ void make_ks_items_kernel(KsItem* items, uint32_t count, const uint32_t* u1, const uint32_t* u2,
+                                     uint32_t cst, uint32_t* out, const uint32_t* ksk) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  KsItem it;
+  it.u1 = u1 + (size_t)t * CT_N;
+  it.u2 = u2 ? u2 + (size_t)t * CT_N : nullptr;
+  it.out = out + (size_t)t * CT_n;
+  it.ksk = ksk;
+  it.cst = cst;
+  it.pad = 0;
+  items[t] = it;
+}
+
+__global__ void negate_kernel(const uint32_t* a, uint32_t* out, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = 0u - a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int launch_bk_transform(const uint32_t* bk_coeff, uint64_t* bk_ntt, const uint64_t* tw_fwd, void* stream) {
+  const uint32_t n_polys = LWE_n * 2 * ELL * 2;
+  // 1/1024 mod p = p - (p - 1) / 1024
+  const uint64_t n_inv = GL_P - (GL_P - 1) / RING_N;
+  hipLaunchKernelGGL(bk_transform_kernel<4>, dim3((n_polys + 3) / 4), dim3(256), 0, S(stream), bk_coeff, bk_ntt, tw_fwd,
+                     n_polys, n_inv);
+  return (int)hipGetLastError();
+}
+
+int launch_ksk_relayout(const uint32_t* ksk_in, uint32_t* ksk_out, void* stream) {
+  hipLaunchKernelGGL(ksk_relayout_kernel, dim3(4096), dim3(256), 0, S(stream), ksk_in, ksk_out);
+  return (int)hipGetLastError();
+}
+
+int launch_br(const BrItem* items, uint32_t count, const uint64_t* tw_fwd, const uint64_t* tw_inv,
+              uint32_t waves_per_block, uint32_t blocks, void* stream) {
+  if (count == 0) return 0;
+  const uint32_t need = (count + waves_per_block - 1) / waves_per_block;
+  if (blocks == 0 || blocks > need) blocks = need;
+  switch (waves_per_block) {
+    case 1: hipLaunchKernelGGL(br_kernel<1>, dim3(blocks), dim3(64), 0, S(stream), items, count, tw_fwd, tw_inv); break;
+    case 2: hipLaunchKernelGGL(br_kernel<2>, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd, tw_inv); break;
+    case 4: hipLaunchKernelGGL(br_kernel<4>, dim3(blocks), dim3(256), 0, S(stream), items, count, tw_fwd, tw_inv); break;
+    case 8: hipLaunchKernelGGL(br_kernel<8>, dim3(blocks), dim3(512), 0, S(stream), items, count, tw_fwd, tw_inv); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream) {
+  if (count == 0) return 0;
+  switch (gates_per_block) {
+    case 4:
+      hipLaunchKernelGGL(ks_kernel<4>, dim3((count + 3) / 4), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
+      break;
+    case 8:
+      hipLaunchKernelGGL(ks_kernel<8>, dim3((count + 7) / 8), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
+      break;
+    case 16:
+      hipLaunchKernelGGL(ks_kernel<16>, dim3((count + 15) / 16), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
+      break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
+                         uint32_t cst, uint32_t mu, uint32_t* out, const uint64_t* bk, void* stream) {
+  if (count == 0) return 0;
+  hipLaunchKernelGGL(make_br_items_kernel, dim3((count + 255) / 256), dim3(256), 0, S(stream), items, count, a, b, ca,
+                     cb, cst, mu, out, bk);
+  return (int)hipGetLastError();
+}
+
+int launch_make_ks_items(KsItem* items, uint32_t count, const uint32_t* u1, const uint32_t* u2, uint32_t cst,
+                         uint32_t* out, const uint32_t* ksk, void* stream) {
+  if (count == 0) return 0;
+  hipLaunchKernelGGL(make_ks_items_kernel, dim3((count + 255) / 256), dim3(256), 0, S(stream), items, count, u1, u2,
+                     cst, out, ksk);
+  return (int)hipGetLastError();
+}
+
+int launch_negate(const uint32_t* a, uint32_t* out, size_t words, void* stream) {
+  if (words == 0) return 0;
+  hipLaunchKernelGGL(negate_kernel, dim3(1024), dim3(256), 0, S(stream), a, out, words);
+  return (int)hipGetLastError();
+}
+
+}  // namespace vlp

@@ -1,0 +1,47 @@
+// Gate netlists of the VeLoPIR circuits and their level schedule (host C++).
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/vlp.h"
+
+namespace vlp {
+
+// Where a ciphertext operand lives.
+enum class Src : uint8_t { None = 0, Query, DbLoc, DbPay, Gate, Const };
+
+struct Operand {
+  Src src = Src::None;
+  uint32_t index = 0;  // ciphertext index within the region (gate id for Src::Gate, bit for Src::Const)
+  static Operand q(uint32_t i) { return {Src::Query, i}; }
+  static Operand loc(uint32_t i) { return {Src::DbLoc, i}; }
+  static Operand pay(uint32_t i) { return {Src::DbPay, i}; }
+  static Operand gate(uint32_t g) { return {Src::Gate, g}; }
+  static Operand cst(int bit) { return {Src::Const, (uint32_t)(bit ? 1 : 0)}; }
+  bool is_const() const { return src == Src::Const; }
+};
+
+struct Gate {
+  uint8_t op;        // vlp_gate_op (AND, XOR, XNOR, MUX, ...)
+  Operand a, b, c;   // MUX(a = select, b = if 1, c = if 0)
+  uint32_t level;    // 1 + max level of the gate operands (inputs are level 0)
+  int32_t out_slot;  // >= 0: written to user output slot (v_out / R), else internal
+};
+
+// Output slots: validation bit of record i -> slot i; aggregated bit j -> slot M + j.
+struct Netlist {
+  std::vector<Gate> gates;
+  uint32_t levels = 0;
+  uint32_t M = 0, l_S = 0;
+  std::vector<Operand> v_of_record;  // M entries
+  std::vector<Operand> result;       // l_S entries (R), may be gates or inputs
+  uint64_t blind_rotations() const;
+  uint64_t key_switches() const;
+};
+
+// Builds the gate netlist of Algorithm 3 for `shape` (validation by IntV,
+// CoV or IdM, zero-out, aggregation).  Returns false for shapes out of range.
+bool build_netlist(const vlp_shape& shape, Netlist& out, const char** why);
+
+}  // namespace vlp

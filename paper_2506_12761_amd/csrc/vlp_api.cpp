@@ -1,0 +1,778 @@
+// Host runtime of libvlp: contexts, keysets, elementwise calls, programs
+// (level-scheduled netlists) and the C ABI declared in include/vlp.h.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <list>
+#include <string>
+#include <vector>
+
+#include "../../include/vlp.h"
+#include "internal.h"
+#include "netlist.h"
+
+using namespace vlp;
+
+struct vlp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, used = 0;
+  std::string err;
+  uint64_t* tw_fwd = nullptr;  // device twiddle tables
+  uint64_t* tw_inv = nullptr;
+  int num_cus = 256;
+  vlp_tuning tune{2, 3, 8};
+  // Grow-only scratch for the elementwise calls.
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  int live_keysets = 0, live_programs = 0;
+  std::list<vlp_program*> eval_cache;  // programs made by vlp_evaluate, most recent first
+};
+
+struct vlp_keyset {
+  vlp_ctx* ctx;
+  uint64_t* bk_ntt;
+  uint32_t* ksk;
+  int users;  // live programs made with it
+};
+
+// A program's per-level work, in device arrays.
+struct Level {
+  uint32_t br_first, br_count;  // range in the program's BR item array
+  uint32_t ks_first, ks_count;  // range in the KS item array
+};
+
+struct vlp_program {
+  vlp_ctx* ctx;
+  vlp_keyset* ks;
+  vlp_shape shape;
+  uint64_t gates = 0, brs = 0, kss = 0;
+  std::vector<Level> levels;
+  uint32_t next_level = 0;
+  BrItem* br_items = nullptr;
+  KsItem* ks_items = nullptr;
+  uint32_t* gate_buf = nullptr;   // internal gate outputs [n_internal][631]
+  uint32_t* ext_buf = nullptr;    // LWE_N slots [max BR per level][1025]
+  size_t bytes = 0;
+  uint32_t max_br_level = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  // arguments, for the vlp_evaluate cache
+  const uint32_t *q, *loc, *pay;
+  uint32_t *R, *v;
+};
+
+namespace {
+
+vlp_status fail(vlp_ctx* ctx, vlp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return st;
+}
+
+std::string g_create_err;
+
+#define HIPCHECK(ctx, expr)                                                                          \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess) return fail((ctx), VLP_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+#define LAUNCHCHECK(ctx, expr)                                                                       \
+  do {                                                                                               \
+    int e_ = (expr);                                                                                 \
+    if (e_ != 0) return fail((ctx), VLP_EHIP, "%s: %s", #expr, hipGetErrorString((hipError_t)e_)); \
+  } while (0)
+
+vlp_status dev_alloc(vlp_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return VLP_OK;
+  if (ctx->used + bytes > ctx->budget)
+    return fail(ctx, VLP_EBUDGET, "allocation of %zu bytes exceeds the budget (%zu of %zu in use)", bytes, ctx->used,
+                ctx->budget);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(ctx, VLP_EHIP, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  ctx->used += bytes;
+  return VLP_OK;
+}
+
+void dev_free(vlp_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->used -= bytes;
+}
+
+vlp_status ensure_scratch(vlp_ctx* ctx, size_t bytes) {
+  if (ctx->scratch_bytes >= bytes) return VLP_OK;
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  dev_free(ctx, ctx->scratch, ctx->scratch_bytes);
+  ctx->scratch = nullptr;
+  ctx->scratch_bytes = 0;
+  size_t want = std::max(bytes, (size_t)1 << 20);
+  vlp_status st = dev_alloc(ctx, &ctx->scratch, want);
+  if (st != VLP_OK) return st;
+  ctx->scratch_bytes = want;
+  return VLP_OK;
+}
+
+bool params_ok(const vlp_params* p) {
+  return p && p->n == (uint32_t)LWE_n && p->N == (uint32_t)RING_N && p->k == 1 && p->bg_bit == (uint32_t)BG_BIT &&
+         p->ell == (uint32_t)ELL && p->ks_basebit == (uint32_t)KS_BASEBIT && p->ks_t == (uint32_t)KS_T;
+}
+
+bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
+  if (!a || !b) return false;
+  const char *pa = (const char*)a, *pb = (const char*)b;
+  return pa < pb + bn && pb < pa + an;
+}
+
+size_t br_blocks(const vlp_ctx* ctx) { return (size_t)ctx->num_cus * ctx->tune.br_blocks_per_cu; }
+
+// Gate pre-combination coefficients (Section 2.2 construction).
+void gate_coeffs(uint8_t op, int32_t* ca, int32_t* cb, uint32_t* cst) {
+  switch (op) {
+    case VLP_AND: *ca = 1; *cb = 1; *cst = 0u - MU; break;
+    case VLP_OR: *ca = 1; *cb = 1; *cst = MU; break;
+    case VLP_NAND: *ca = -1; *cb = -1; *cst = MU; break;
+    case VLP_XOR: *ca = 2; *cb = 2; *cst = 2 * MU; break;
+    case VLP_XNOR: *ca = -2; *cb = -2; *cst = 0u - 2 * MU; break;
+    default: *ca = 1; *cb = 1; *cst = 0u - MU; break;  // MUX first unit
+  }
+}
+
+uint32_t encode_bit(uint32_t bit) { return bit ? MU : 0u - MU; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+extern "C" const char* vlp_version(void) { return "vlp 0.1 (gfx950, Goldilocks NTT)"; }
+
+extern "C" void vlp_default_params(vlp_params* p) {
+  if (!p) return;
+  p->n = LWE_n;
+  p->N = RING_N;
+  p->k = 1;
+  p->bg_bit = BG_BIT;
+  p->ell = ELL;
+  p->ks_basebit = KS_BASEBIT;
+  p->ks_t = KS_T;
+}
+
+extern "C" const char* vlp_last_error(const vlp_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+extern "C" vlp_status vlp_ctx_create(vlp_ctx** out, const vlp_params* p, int device, void* hip_stream, size_t hbm_budget) {
+  if (!out) {
+    g_create_err = "out is NULL";
+    return VLP_EINVAL;
+  }
+  *out = nullptr;
+  if (!params_ok(p)) {
+    g_create_err = "parameters differ from the supported set {630, 1024, 1, 7, 3, 2, 8}";
+    return VLP_EPARAM;
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev) {
+    g_create_err = std::string("no such HIP device: ") + (e != hipSuccess ? hipGetErrorString(e) : "index out of range");
+    return VLP_EHIP;
+  }
+  vlp_ctx* ctx = new vlp_ctx();
+  ctx->device = device;
+  e = hipSetDevice(device);
+  if (e == hipSuccess) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e == hipSuccess) {
+      ctx->num_cus = prop.multiProcessorCount;
+      size_t total = prop.totalGlobalMem;
+      ctx->budget = hbm_budget ? hbm_budget : total / 10 * 9;
+    }
+  }
+  if (e == hipSuccess) {
+    if (hip_stream) {
+      ctx->stream = (hipStream_t)hip_stream;
+    } else {
+      e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+      ctx->own_stream = e == hipSuccess;
+    }
+  }
+  if (e != hipSuccess) {
+    g_create_err = std::string("HIP set-up failed: ") + hipGetErrorString(e);
+    delete ctx;
+    return VLP_EHIP;
+  }
+  std::vector<uint64_t> tf(RING_N), ti(RING_N);
+  make_twiddles(tf.data(), ti.data());
+  vlp_status st = dev_alloc(ctx, (void**)&ctx->tw_fwd, RING_N * 8);
+  if (st == VLP_OK) st = dev_alloc(ctx, (void**)&ctx->tw_inv, RING_N * 8);
+  if (st == VLP_OK) {
+    e = hipMemcpy(ctx->tw_fwd, tf.data(), RING_N * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->tw_inv, ti.data(), RING_N * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = fail(ctx, VLP_EHIP, "twiddle upload: %s", hipGetErrorString(e));
+  }
+  if (st != VLP_OK) {
+    g_create_err = ctx->err;
+    dev_free(ctx, ctx->tw_fwd, RING_N * 8);
+    dev_free(ctx, ctx->tw_inv, RING_N * 8);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return VLP_OK;
+}
+
+static void program_free(vlp_program* prog);
+
+extern "C" vlp_status vlp_ctx_destroy(vlp_ctx* ctx) {
+  if (!ctx) return VLP_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (vlp_program* p : ctx->eval_cache) program_free(p);
+  ctx->eval_cache.clear();
+  if (ctx->live_keysets || ctx->live_programs)
+    return fail(ctx, VLP_EBUSY, "%d keysets and %d programs still alive", ctx->live_keysets, ctx->live_programs);
+  dev_free(ctx, ctx->scratch, ctx->scratch_bytes);
+  dev_free(ctx, ctx->tw_fwd, RING_N * 8);
+  dev_free(ctx, ctx->tw_inv, RING_N * 8);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_mem_info(const vlp_ctx* ctx, size_t* used, size_t* budget) {
+  if (!ctx) return VLP_EINVAL;
+  if (used) *used = ctx->used;
+  if (budget) *budget = ctx->budget;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_sync(vlp_ctx* ctx) {
+  if (!ctx) return VLP_EINVAL;
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_get_tuning(const vlp_ctx* ctx, vlp_tuning* t) {
+  if (!ctx || !t) return VLP_EINVAL;
+  *t = ctx->tune;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_set_tuning(vlp_ctx* ctx, const vlp_tuning* t) {
+  if (!ctx || !t) return VLP_EINVAL;
+  const uint32_t w = t->br_waves_per_block, g = t->ks_gates_per_block;
+  if (!(w == 1 || w == 2 || w == 4 || w == 8)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2, 4 or 8");
+  if (t->br_blocks_per_cu < 1 || t->br_blocks_per_cu > 64) return fail(ctx, VLP_EINVAL, "br_blocks_per_cu out of [1, 64]");
+  if (!(g == 4 || g == 8 || g == 16)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 4, 8 or 16");
+  ctx->tune = *t;
+  return VLP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Keysets
+// ---------------------------------------------------------------------------
+extern "C" vlp_status vlp_keyset_load(vlp_ctx* ctx, const uint32_t* bk_dev, const uint32_t* ksk_dev, vlp_keyset** out) {
+  if (!ctx) return VLP_EINVAL;
+  if (!bk_dev || !ksk_dev || !out) return fail(ctx, VLP_EINVAL, "null argument");
+  *out = nullptr;
+  vlp_keyset* ks = new vlp_keyset{ctx, nullptr, nullptr, 0};
+  vlp_status st = dev_alloc(ctx, (void**)&ks->bk_ntt, BK_NTT_WORDS * 8);
+  if (st == VLP_OK) st = dev_alloc(ctx, (void**)&ks->ksk, KSK_WORDS * 4);
+  if (st != VLP_OK) {
+    dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 8);
+    delete ks;
+    return st;
+  }
+  int e = launch_bk_transform(bk_dev, ks->bk_ntt, ctx->tw_fwd, ctx->stream);
+  if (e == 0) e = launch_ksk_relayout(ksk_dev, ks->ksk, ctx->stream);
+  if (e != 0) {
+    dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 8);
+    dev_free(ctx, ks->ksk, KSK_WORDS * 4);
+    delete ks;
+    return fail(ctx, VLP_EHIP, "key preparation launch: %s", hipGetErrorString((hipError_t)e));
+  }
+  ctx->live_keysets++;
+  *out = ks;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_keyset_destroy(vlp_keyset* ks) {
+  if (!ks) return VLP_EINVAL;
+  vlp_ctx* ctx = ks->ctx;
+  // Programs cached by vlp_evaluate for this keyset go first.
+  for (auto it = ctx->eval_cache.begin(); it != ctx->eval_cache.end();) {
+    if ((*it)->ks == ks) {
+      (void)hipStreamSynchronize(ctx->stream);
+      program_free(*it);
+      it = ctx->eval_cache.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  if (ks->users) return fail(ctx, VLP_EBUSY, "keyset still used by %d programs", ks->users);
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 8);
+  dev_free(ctx, ks->ksk, KSK_WORDS * 4);
+  ctx->live_keysets--;
+  delete ks;
+  return VLP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise calls
+// ---------------------------------------------------------------------------
+extern "C" vlp_status vlp_bootstrap(vlp_ctx* ctx, const vlp_keyset* ks, const uint32_t* in_dev, uint32_t* out_dev,
+                                    uint32_t mu, size_t B) {
+  if (!ctx) return VLP_EINVAL;
+  if (B == 0) return VLP_OK;
+  if (!ks || ks->ctx != ctx || !in_dev || !out_dev) return fail(ctx, VLP_EINVAL, "null or foreign argument");
+  if (B > (1u << 26)) return fail(ctx, VLP_EINVAL, "B too large");
+  if (ranges_overlap(in_dev, B * CT_n * 4, out_dev, B * CT_N * 4)) return fail(ctx, VLP_EINVAL, "in and out overlap");
+  vlp_status st = ensure_scratch(ctx, B * sizeof(BrItem));
+  if (st != VLP_OK) return st;
+  BrItem* items = (BrItem*)ctx->scratch;
+  LAUNCHCHECK(ctx, launch_make_br_items(items, (uint32_t)B, in_dev, nullptr, 1, 0, 0, mu, out_dev, ks->bk_ntt, ctx->stream));
+  LAUNCHCHECK(ctx, launch_br(items, (uint32_t)B, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
+                             (uint32_t)br_blocks(ctx), ctx->stream));
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_keyswitch(vlp_ctx* ctx, const vlp_keyset* ks, const uint32_t* in_dev, uint32_t* out_dev,
+                                    size_t B) {
+  if (!ctx) return VLP_EINVAL;
+  if (B == 0) return VLP_OK;
+  if (!ks || ks->ctx != ctx || !in_dev || !out_dev) return fail(ctx, VLP_EINVAL, "null or foreign argument");
+  if (B > (1u << 26)) return fail(ctx, VLP_EINVAL, "B too large");
+  if (ranges_overlap(in_dev, B * CT_N * 4, out_dev, B * CT_n * 4)) return fail(ctx, VLP_EINVAL, "in and out overlap");
+  vlp_status st = ensure_scratch(ctx, B * sizeof(KsItem));
+  if (st != VLP_OK) return st;
+  KsItem* items = (KsItem*)ctx->scratch;
+  LAUNCHCHECK(ctx, launch_make_ks_items(items, (uint32_t)B, in_dev, nullptr, 0, out_dev, ks->ksk, ctx->stream));
+  LAUNCHCHECK(ctx, launch_ks_group(items, (uint32_t)B, ks->ksk, ctx->tune.ks_gates_per_block, ctx->stream));
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_gate(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const uint32_t* a_dev,
+                               const uint32_t* b_dev, const uint32_t* c_dev, uint32_t* out_dev, size_t B) {
+  if (!ctx) return VLP_EINVAL;
+  if (op < VLP_AND || op > VLP_MUX) return fail(ctx, VLP_EINVAL, "unknown gate op %d", (int)op);
+  if (B == 0) return VLP_OK;
+  if (!ks || ks->ctx != ctx || !a_dev || !out_dev) return fail(ctx, VLP_EINVAL, "null or foreign argument");
+  if (op != VLP_NOT && !b_dev) return fail(ctx, VLP_EINVAL, "b is NULL");
+  if ((op == VLP_MUX) != (c_dev != nullptr)) return fail(ctx, VLP_EINVAL, "c must be given for MUX only");
+  if (B > (1u << 26)) return fail(ctx, VLP_EINVAL, "B too large");
+  const size_t nb = B * CT_n * 4;
+  if (ranges_overlap(a_dev, nb, out_dev, nb) || ranges_overlap(b_dev, nb, out_dev, nb) ||
+      ranges_overlap(c_dev, nb, out_dev, nb))
+    return fail(ctx, VLP_EINVAL, "output overlaps an input");
+  if (op == VLP_NOT) {
+    LAUNCHCHECK(ctx, launch_negate(a_dev, out_dev, B * CT_n, ctx->stream));
+    return VLP_OK;
+  }
+  const size_t units = op == VLP_MUX ? 2 * B : B;
+  const size_t ext_bytes = (units * CT_N * 4 + 255) & ~(size_t)255;
+  const size_t br_bytes = units * sizeof(BrItem), ks_bytes = B * sizeof(KsItem);
+  vlp_status st = ensure_scratch(ctx, ext_bytes + br_bytes + ks_bytes + 256);
+  if (st != VLP_OK) return st;
+  uint32_t* ext = (uint32_t*)ctx->scratch;
+  BrItem* bri = (BrItem*)((char*)ctx->scratch + ext_bytes);
+  KsItem* ksi = (KsItem*)((char*)bri + br_bytes);
+  int32_t ca, cb;
+  uint32_t cst;
+  gate_coeffs((uint8_t)op, &ca, &cb, &cst);
+  LAUNCHCHECK(ctx, launch_make_br_items(bri, (uint32_t)B, a_dev, b_dev, ca, cb, cst, MU, ext, ks->bk_ntt, ctx->stream));
+  if (op == VLP_MUX)
+    LAUNCHCHECK(ctx, launch_make_br_items(bri + B, (uint32_t)B, a_dev, c_dev, -1, 1, 0u - MU, MU, ext + B * CT_N,
+                                          ks->bk_ntt, ctx->stream));
+  LAUNCHCHECK(ctx, launch_br(bri, (uint32_t)units, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
+                             (uint32_t)br_blocks(ctx), ctx->stream));
+  LAUNCHCHECK(ctx, launch_make_ks_items(ksi, (uint32_t)B, ext, op == VLP_MUX ? ext + B * CT_N : nullptr,
+                                        op == VLP_MUX ? MU : 0u, out_dev, ks->ksk, ctx->stream));
+  LAUNCHCHECK(ctx, launch_ks_group(ksi, (uint32_t)B, ks->ksk, ctx->tune.ks_gates_per_block, ctx->stream));
+  return VLP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Programs
+// ---------------------------------------------------------------------------
+static void program_free(vlp_program* prog) {
+  vlp_ctx* ctx = prog->ctx;
+  if (prog->graph_exec) (void)hipGraphExecDestroy(prog->graph_exec);
+  if (prog->graph) (void)hipGraphDestroy(prog->graph);
+  dev_free(ctx, prog->br_items, 0);
+  dev_free(ctx, prog->ks_items, 0);
+  dev_free(ctx, prog->gate_buf, 0);
+  dev_free(ctx, prog->ext_buf, 0);
+  ctx->used -= prog->bytes;
+  prog->ks->users--;
+  ctx->live_programs--;
+  delete prog;
+}
+
+static vlp_status shape_words(const vlp_shape* sh, size_t* q, size_t* loc, size_t* pay) {
+  const size_t M = sh->M, l = sh->l_I, d = sh->mode == VLP_IDM ? 1 : sh->d;
+  *q = d * l;
+  *loc = sh->mode == VLP_INTV ? M * d * 2 * l : M * d * l;
+  *pay = M * sh->l_S;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_plan_counts(const vlp_shape* shape, uint64_t* gates, uint64_t* brs, uint64_t* kss,
+                                      uint32_t* levels) {
+  if (!shape) return VLP_EINVAL;
+  Netlist nl;
+  const char* why = "";
+  if (!build_netlist(*shape, nl, &why)) return VLP_EINVAL;
+  if (gates) *gates = nl.gates.size();
+  if (brs) *brs = nl.blind_rotations();
+  if (kss) *kss = nl.key_switches();
+  if (levels) *levels = nl.levels;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, const vlp_shape* shape,
+                                         const uint32_t* query_dev, const uint32_t* db_loc_dev,
+                                         const uint32_t* db_pay_dev, uint32_t* R_dev, uint32_t* v_out_dev,
+                                         vlp_program** out) {
+  if (!ctx) return VLP_EINVAL;
+  vlp_keyset* ks = const_cast<vlp_keyset*>(ks_c);
+  if (!ks || ks->ctx != ctx || !shape || !out || !query_dev || !db_loc_dev)
+    return fail(ctx, VLP_EINVAL, "null or foreign argument");
+  *out = nullptr;
+  if (shape->l_S > 0 && (!db_pay_dev || !R_dev)) return fail(ctx, VLP_EINVAL, "l_S > 0 needs db_pay and R");
+  Netlist nl;
+  const char* why = "";
+  if (!build_netlist(*shape, nl, &why)) return fail(ctx, VLP_EINVAL, "bad shape: %s", why);
+  size_t wq, wl, wp;
+  shape_words(shape, &wq, &wl, &wp);
+  const size_t M = nl.M, lS = nl.l_S;
+  if (ranges_overlap(R_dev, lS * CT_n * 4, v_out_dev, M * CT_n * 4))
+    return fail(ctx, VLP_EINVAL, "R and v_out overlap");
+  for (const void* in : {(const void*)query_dev, (const void*)db_loc_dev, (const void*)db_pay_dev}) {
+    const size_t inb = in == query_dev ? wq * CT_n * 4 : (in == db_loc_dev ? wl * CT_n * 4 : wp * CT_n * 4);
+    if (ranges_overlap(in, inb, R_dev, lS * CT_n * 4) || ranges_overlap(in, inb, v_out_dev, M * CT_n * 4))
+      return fail(ctx, VLP_EINVAL, "an output overlaps an input");
+  }
+
+  // Output slots: v of record i -> v_out[i] (if given); R[j] -> R[j].
+  std::vector<int32_t> slot(nl.gates.size(), -1);
+  if (v_out_dev)
+    for (size_t i = 0; i < M; ++i)
+      if (nl.v_of_record[i].src == Src::Gate) slot[nl.v_of_record[i].index] = (int32_t)i;
+  for (size_t j = 0; j < lS; ++j) {
+    const Operand& r = nl.result[j];
+    if (r.src != Src::Gate || slot[r.index] >= 0)
+      return fail(ctx, VLP_EINVAL, "unsupported shape: result bit %zu is not a distinct gate", j);
+    slot[r.index] = (int32_t)(M + j);
+  }
+  // Internal storage for the other gates.
+  std::vector<uint32_t> internal(nl.gates.size(), 0);
+  uint32_t n_internal = 0;
+  for (size_t g = 0; g < nl.gates.size(); ++g)
+    if (slot[g] < 0) internal[g] = n_internal++;
+
+  // Gates by level.
+  std::vector<std::vector<uint32_t>> by_level(nl.levels + 1);
+  for (size_t g = 0; g < nl.gates.size(); ++g) by_level[nl.gates[g].level].push_back((uint32_t)g);
+  uint32_t max_br = 0;
+  for (uint32_t L = 1; L <= nl.levels; ++L) {
+    uint32_t nbr = 0;
+    for (uint32_t g : by_level[L]) nbr += nl.gates[g].op == VLP_MUX ? 2 : 1;
+    max_br = std::max(max_br, nbr);
+  }
+  const uint64_t n_br = nl.blind_rotations(), n_ks = nl.key_switches();
+  const size_t b_items = n_br * sizeof(BrItem), k_items = n_ks * sizeof(KsItem);
+  const size_t b_gate = (size_t)n_internal * CT_n * 4, b_ext = (size_t)max_br * CT_N * 4;
+  const size_t total = b_items + k_items + b_gate + b_ext;
+  if (ctx->used + total > ctx->budget)
+    return fail(ctx, VLP_EBUDGET, "program needs %zu bytes; %zu of %zu in use", total, ctx->used, ctx->budget);
+
+  vlp_program* prog = new vlp_program();
+  prog->ctx = ctx;
+  prog->ks = ks;
+  prog->shape = *shape;
+  prog->gates = nl.gates.size();
+  prog->brs = n_br;
+  prog->kss = n_ks;
+  prog->max_br_level = max_br;
+  prog->q = query_dev;
+  prog->loc = db_loc_dev;
+  prog->pay = db_pay_dev;
+  prog->R = R_dev;
+  prog->v = v_out_dev;
+  hipError_t e = hipSuccess;
+  if (b_items) e = hipMalloc((void**)&prog->br_items, b_items);
+  if (e == hipSuccess && k_items) e = hipMalloc((void**)&prog->ks_items, k_items);
+  if (e == hipSuccess && b_gate) e = hipMalloc((void**)&prog->gate_buf, b_gate);
+  if (e == hipSuccess && b_ext) e = hipMalloc((void**)&prog->ext_buf, b_ext);
+  if (e != hipSuccess) {
+    (void)hipFree(prog->br_items);
+    (void)hipFree(prog->ks_items);
+    (void)hipFree(prog->gate_buf);
+    (void)hipFree(prog->ext_buf);
+    delete prog;
+    return fail(ctx, VLP_EHIP, "program allocation: %s", hipGetErrorString(e));
+  }
+  prog->bytes = total;
+  ctx->used += total;
+  ks->users++;
+  ctx->live_programs++;
+
+  // Resolve operands to device pointers.
+  auto ptr = [&](const Operand& o) -> const uint32_t* {
+    switch (o.src) {
+      case Src::Query: return query_dev + (size_t)o.index * CT_n;
+      case Src::DbLoc: return db_loc_dev + (size_t)o.index * CT_n;
+      case Src::DbPay: return db_pay_dev + (size_t)o.index * CT_n;
+      case Src::Gate: {
+        const int32_t s = slot[o.index];
+        if (s < 0) return prog->gate_buf + (size_t)internal[o.index] * CT_n;
+        if ((size_t)s < M) return v_out_dev + (size_t)s * CT_n;
+        return R_dev + (size_t)(s - M) * CT_n;
+      }
+      default: return nullptr;
+    }
+  };
+  // A BR unit: (0, cst) + ca * x + cb * y, with trivial operands folded into cst.
+  auto unit = [&](int32_t ca, Operand x, int32_t cb, Operand y, uint32_t cst, uint32_t* out) {
+    BrItem it{};
+    if (x.is_const()) {
+      cst += (uint32_t)ca * encode_bit(x.index);
+      ca = 0;
+    }
+    if (y.is_const()) {
+      cst += (uint32_t)cb * encode_bit(y.index);
+      cb = 0;
+    }
+    const uint32_t* px = ca ? ptr(x) : nullptr;
+    const uint32_t* py = cb ? ptr(y) : nullptr;
+    if (!px) {  // the kernel needs the first operand
+      px = py;
+      ca = cb;
+      py = nullptr;
+      cb = 0;
+    }
+    it.a = px;
+    it.b = py;
+    it.ca = ca;
+    it.cb = cb;
+    it.cst = cst;
+    it.mu = MU;
+    it.out = out;
+    it.bk = ks->bk_ntt;
+    return it;
+  };
+  std::vector<BrItem> hb;
+  std::vector<KsItem> hk;
+  hb.reserve(n_br);
+  hk.reserve(n_ks);
+  for (uint32_t L = 1; L <= nl.levels; ++L) {
+    Level lv{(uint32_t)hb.size(), 0, (uint32_t)hk.size(), 0};
+    uint32_t e_slot = 0;
+    for (uint32_t g : by_level[L]) {
+      const Gate& G = nl.gates[g];
+      uint32_t* gout = const_cast<uint32_t*>(ptr(Operand::gate(g)));
+      KsItem k{};
+      k.out = gout;
+      k.ksk = ks->ksk;
+      if (G.op == VLP_MUX) {
+        uint32_t* u1 = prog->ext_buf + (size_t)e_slot++ * CT_N;
+        uint32_t* u2 = prog->ext_buf + (size_t)e_slot++ * CT_N;
+        hb.push_back(unit(1, G.a, 1, G.b, 0u - MU, u1));
+        hb.push_back(unit(-1, G.a, 1, G.c, 0u - MU, u2));
+        k.u1 = u1;
+        k.u2 = u2;
+        k.cst = MU;
+      } else {
+        int32_t ca, cb;
+        uint32_t cst;
+        gate_coeffs(G.op, &ca, &cb, &cst);
+        uint32_t* u1 = prog->ext_buf + (size_t)e_slot++ * CT_N;
+        hb.push_back(unit(ca, G.a, cb, G.b, cst, u1));
+        k.u1 = u1;
+        k.u2 = nullptr;
+        k.cst = 0;
+      }
+      hk.push_back(k);
+    }
+    lv.br_count = (uint32_t)hb.size() - lv.br_first;
+    lv.ks_count = (uint32_t)hk.size() - lv.ks_first;
+    prog->levels.push_back(lv);
+  }
+  if (b_items) e = hipMemcpy(prog->br_items, hb.data(), b_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess && k_items) e = hipMemcpy(prog->ks_items, hk.data(), k_items, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    program_free(prog);
+    return fail(ctx, VLP_EHIP, "program upload: %s", hipGetErrorString(e));
+  }
+  *out = prog;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_program_reset(vlp_program* prog) {
+  if (!prog) return VLP_EINVAL;
+  prog->next_level = 0;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_program_counts(const vlp_program* prog, uint64_t* gates, uint64_t* brs, uint64_t* kss,
+                                         uint32_t* levels) {
+  if (!prog) return VLP_EINVAL;
+  if (gates) *gates = prog->gates;
+  if (brs) *brs = prog->brs;
+  if (kss) *kss = prog->kss;
+  if (levels) *levels = (uint32_t)prog->levels.size();
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_program_destroy(vlp_program* prog) {
+  if (!prog) return VLP_EINVAL;
+  vlp_ctx* ctx = prog->ctx;
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  program_free(prog);
+  return VLP_OK;
+}
+
+static vlp_status run_level(vlp_ctx* ctx, vlp_program* prog, uint32_t L) {
+  const Level& lv = prog->levels[L];
+  LAUNCHCHECK(ctx, launch_br(prog->br_items + lv.br_first, lv.br_count, ctx->tw_fwd, ctx->tw_inv,
+                             ctx->tune.br_waves_per_block, (uint32_t)br_blocks(ctx), ctx->stream));
+  LAUNCHCHECK(ctx, launch_ks_group(prog->ks_items + lv.ks_first, lv.ks_count, prog->ks->ksk,
+                                   ctx->tune.ks_gates_per_block, ctx->stream));
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_step(vlp_ctx* ctx, vlp_program* const* progs, size_t n, size_t* remaining) {
+  if (!ctx) return VLP_EINVAL;
+  if (n && !progs) return fail(ctx, VLP_EINVAL, "progs is NULL");
+  // Gather this step's BR and KS items of every unfinished program into one batch.
+  size_t nbr = 0, nks = 0, left = 0;
+  for (size_t p = 0; p < n; ++p) {
+    vlp_program* pr = progs[p];
+    if (!pr || pr->ctx != ctx) return fail(ctx, VLP_EINVAL, "null or foreign program");
+    if (pr->next_level < pr->levels.size()) {
+      nbr += pr->levels[pr->next_level].br_count;
+      nks += pr->levels[pr->next_level].ks_count;
+    }
+  }
+  if (nbr) {
+    const size_t bytes = nbr * sizeof(BrItem) + nks * sizeof(KsItem) + 256;
+    vlp_status st = ensure_scratch(ctx, bytes);
+    if (st != VLP_OK) return st;
+    BrItem* bri = (BrItem*)ctx->scratch;
+    KsItem* ksi = (KsItem*)((char*)ctx->scratch + ((nbr * sizeof(BrItem) + 255) & ~(size_t)255));
+    size_t ob = 0, ok = 0;
+    std::vector<std::pair<size_t, size_t>> ks_groups;  // (first, count) per program
+    for (size_t p = 0; p < n; ++p) {
+      vlp_program* pr = progs[p];
+      if (pr->next_level >= pr->levels.size()) continue;
+      const Level& lv = pr->levels[pr->next_level];
+      HIPCHECK(ctx, hipMemcpyAsync(bri + ob, pr->br_items + lv.br_first, lv.br_count * sizeof(BrItem),
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHECK(ctx, hipMemcpyAsync(ksi + ok, pr->ks_items + lv.ks_first, lv.ks_count * sizeof(KsItem),
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+      ks_groups.push_back({ok, lv.ks_count});
+      ob += lv.br_count;
+      ok += lv.ks_count;
+    }
+    LAUNCHCHECK(ctx, launch_br(bri, (uint32_t)nbr, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
+                               (uint32_t)br_blocks(ctx), ctx->stream));
+    size_t gi = 0;
+    for (size_t p = 0; p < n; ++p) {
+      vlp_program* pr = progs[p];
+      if (pr->next_level >= pr->levels.size()) continue;
+      LAUNCHCHECK(ctx, launch_ks_group(ksi + ks_groups[gi].first, (uint32_t)ks_groups[gi].second, pr->ks->ksk,
+                                       ctx->tune.ks_gates_per_block, ctx->stream));
+      gi++;
+    }
+  }
+  for (size_t p = 0; p < n; ++p) {
+    vlp_program* pr = progs[p];
+    if (pr->next_level < pr->levels.size()) pr->next_level++;
+    if (pr->next_level < pr->levels.size()) left++;
+  }
+  if (remaining) *remaining = left;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_program_run(vlp_ctx* ctx, vlp_program* prog, int use_graph) {
+  if (!ctx || !prog || prog->ctx != ctx) return ctx ? fail(ctx, VLP_EINVAL, "null or foreign program") : VLP_EINVAL;
+  if (!use_graph) {
+    for (uint32_t L = prog->next_level; L < prog->levels.size(); ++L) {
+      vlp_status st = run_level(ctx, prog, L);
+      if (st != VLP_OK) return st;
+    }
+    prog->next_level = (uint32_t)prog->levels.size();
+    return VLP_OK;
+  }
+  if (!prog->graph_exec) {
+    HIPCHECK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    vlp_status st = VLP_OK;
+    for (uint32_t L = 0; L < prog->levels.size() && st == VLP_OK; ++L) st = run_level(ctx, prog, L);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (st != VLP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(ctx, VLP_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&prog->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(ctx, VLP_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    prog->graph = g;
+  }
+  HIPCHECK(ctx, hipGraphLaunch(prog->graph_exec, ctx->stream));
+  prog->next_level = (uint32_t)prog->levels.size();
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_evaluate(vlp_ctx* ctx, const vlp_keyset* ks, const vlp_shape* shape,
+                                   const uint32_t* query_dev, const uint32_t* db_loc_dev, const uint32_t* db_pay_dev,
+                                   uint32_t* R_dev, uint32_t* v_out_dev) {
+  if (!ctx) return VLP_EINVAL;
+  if (!shape) return fail(ctx, VLP_EINVAL, "shape is NULL");
+  vlp_program* prog = nullptr;
+  for (auto it = ctx->eval_cache.begin(); it != ctx->eval_cache.end(); ++it) {
+    vlp_program* p = *it;
+    if (p->ks == ks && memcmp(&p->shape, shape, sizeof(vlp_shape)) == 0 && p->q == query_dev &&
+        p->loc == db_loc_dev && p->pay == db_pay_dev && p->R == R_dev && p->v == v_out_dev) {
+      prog = p;
+      ctx->eval_cache.erase(it);
+      break;
+    }
+  }
+  if (!prog) {
+    vlp_status st = vlp_program_create(ctx, ks, shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev, &prog);
+    if (st == VLP_EBUDGET && !ctx->eval_cache.empty()) {
+      // Make room by dropping cached programs, then retry once.
+      (void)hipStreamSynchronize(ctx->stream);
+      for (vlp_program* p : ctx->eval_cache) program_free(p);
+      ctx->eval_cache.clear();
+      st = vlp_program_create(ctx, ks, shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev, &prog);
+    }
+    if (st != VLP_OK) return st;
+  }
+  ctx->eval_cache.push_front(prog);
+  while (ctx->eval_cache.size() > 8) {
+    (void)hipStreamSynchronize(ctx->stream);
+    program_free(ctx->eval_cache.back());
+    ctx->eval_cache.pop_back();
+  }
+  prog->next_level = 0;
+  return vlp_program_run(ctx, prog, 1);
+}
