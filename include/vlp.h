@@ -200,6 +200,18 @@ typedef struct {
 vlp_status vlp_get_tuning(const vlp_ctx *ctx, vlp_tuning *t);
 vlp_status vlp_set_tuning(vlp_ctx *ctx, const vlp_tuning *t);
 
+/* ---- Kernel timing.  While enabled, every blind-rotation and key-switching
+ * kernel launch the context makes outside graph capture is bracketed by HIP
+ * events on the context's stream.  vlp_profile_read waits for the stream,
+ * returns the totals since the last read (or enable) and clears them. */
+typedef struct {
+    uint64_t launches;  /* kernel launches timed */
+    uint64_t items;     /* blind rotations (or key switches) they processed */
+    double ms;          /* summed launch durations, milliseconds */
+} vlp_kernel_stats;
+vlp_status vlp_profile_enable(vlp_ctx *ctx, int enable);
+vlp_status vlp_profile_read(vlp_ctx *ctx, vlp_kernel_stats *br, vlp_kernel_stats *ks);
+
 /* Wait until all work enqueued on the context's stream has finished. */
 vlp_status vlp_sync(vlp_ctx *ctx);
 

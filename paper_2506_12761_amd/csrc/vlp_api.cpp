@@ -31,6 +31,11 @@ struct vlp_ctx {
   size_t scratch_bytes = 0;
   int live_keysets = 0, live_programs = 0;
   std::list<vlp_program*> eval_cache;  // programs made by vlp_evaluate, most recent first
+  // Kernel timing (vlp_profile_enable).
+  bool prof = false;
+  struct Mark { hipEvent_t e0, e1; int kind; uint64_t items; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
 };
 
 struct vlp_keyset {
@@ -139,6 +144,60 @@ bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
 
 size_t br_blocks(const vlp_ctx* ctx) { return (size_t)ctx->num_cus * ctx->tune.br_blocks_per_cu; }
 
+int mark_begin(vlp_ctx* ctx);
+void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
+
+int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
+  if (count == 0) return 0;
+  const int m = mark_begin(ctx);
+  const int e = launch_br(items, count, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
+                          (uint32_t)br_blocks(ctx), ctx->stream);
+  mark_end(ctx, m, 0, count);
+  return e;
+}
+
+int timed_ks(vlp_ctx* ctx, const KsItem* items, uint32_t count, const uint32_t* ksk) {
+  if (count == 0) return 0;
+  const int m = mark_begin(ctx);
+  const int e = launch_ks_group(items, count, ksk, ctx->tune.ks_gates_per_block, ctx->stream);
+  mark_end(ctx, m, 1, count);
+  return e;
+}
+
+hipEvent_t take_event(vlp_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+bool capturing(vlp_ctx* ctx) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(ctx->stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// Opens a timed region around one kernel launch (kind 0 = blind rotation, 1 = key switch).
+int mark_begin(vlp_ctx* ctx) {
+  if (!ctx->prof || capturing(ctx)) return -1;
+  vlp_ctx::Mark m{take_event(ctx), take_event(ctx), 0, 0};
+  if (!m.e0 || !m.e1) return -1;
+  (void)hipEventRecord(m.e0, ctx->stream);
+  ctx->marks.push_back(m);
+  return (int)ctx->marks.size() - 1;
+}
+
+void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items) {
+  if (id < 0) return;
+  vlp_ctx::Mark& m = ctx->marks[(size_t)id];
+  m.kind = kind;
+  m.items = items;
+  (void)hipEventRecord(m.e1, ctx->stream);
+}
+
 // Gate pre-combination coefficients (Section 2.2 construction).
 void gate_coeffs(uint8_t op, int32_t* ca, int32_t* cb, uint32_t* cst) {
   switch (op) {
@@ -244,6 +303,11 @@ extern "C" vlp_status vlp_ctx_destroy(vlp_ctx* ctx) {
   ctx->eval_cache.clear();
   if (ctx->live_keysets || ctx->live_programs)
     return fail(ctx, VLP_EBUSY, "%d keysets and %d programs still alive", ctx->live_keysets, ctx->live_programs);
+  for (const auto& m : ctx->marks) {
+    ctx->event_pool.push_back(m.e0);
+    ctx->event_pool.push_back(m.e1);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   dev_free(ctx, ctx->scratch, ctx->scratch_bytes);
   dev_free(ctx, ctx->tw_fwd, RING_N * 8);
   dev_free(ctx, ctx->tw_inv, RING_N * 8);
@@ -345,8 +409,7 @@ extern "C" vlp_status vlp_bootstrap(vlp_ctx* ctx, const vlp_keyset* ks, const ui
   if (st != VLP_OK) return st;
   BrItem* items = (BrItem*)ctx->scratch;
   LAUNCHCHECK(ctx, launch_make_br_items(items, (uint32_t)B, in_dev, nullptr, 1, 0, 0, mu, out_dev, ks->bk_ntt, ctx->stream));
-  LAUNCHCHECK(ctx, launch_br(items, (uint32_t)B, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
-                             (uint32_t)br_blocks(ctx), ctx->stream));
+  LAUNCHCHECK(ctx, timed_br(ctx, items, (uint32_t)B));
   return VLP_OK;
 }
 
@@ -361,7 +424,7 @@ extern "C" vlp_status vlp_keyswitch(vlp_ctx* ctx, const vlp_keyset* ks, const ui
   if (st != VLP_OK) return st;
   KsItem* items = (KsItem*)ctx->scratch;
   LAUNCHCHECK(ctx, launch_make_ks_items(items, (uint32_t)B, in_dev, nullptr, 0, out_dev, ks->ksk, ctx->stream));
-  LAUNCHCHECK(ctx, launch_ks_group(items, (uint32_t)B, ks->ksk, ctx->tune.ks_gates_per_block, ctx->stream));
+  LAUNCHCHECK(ctx, timed_ks(ctx, items, (uint32_t)B, ks->ksk));
   return VLP_OK;
 }
 
@@ -397,11 +460,10 @@ extern "C" vlp_status vlp_gate(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op o
   if (op == VLP_MUX)
     LAUNCHCHECK(ctx, launch_make_br_items(bri + B, (uint32_t)B, a_dev, c_dev, -1, 1, 0u - MU, MU, ext + B * CT_N,
                                           ks->bk_ntt, ctx->stream));
-  LAUNCHCHECK(ctx, launch_br(bri, (uint32_t)units, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
-                             (uint32_t)br_blocks(ctx), ctx->stream));
+  LAUNCHCHECK(ctx, timed_br(ctx, bri, (uint32_t)units));
   LAUNCHCHECK(ctx, launch_make_ks_items(ksi, (uint32_t)B, ext, op == VLP_MUX ? ext + B * CT_N : nullptr,
                                         op == VLP_MUX ? MU : 0u, out_dev, ks->ksk, ctx->stream));
-  LAUNCHCHECK(ctx, launch_ks_group(ksi, (uint32_t)B, ks->ksk, ctx->tune.ks_gates_per_block, ctx->stream));
+  LAUNCHCHECK(ctx, timed_ks(ctx, ksi, (uint32_t)B, ks->ksk));
   return VLP_OK;
 }
 
@@ -648,10 +710,8 @@ extern "C" vlp_status vlp_program_destroy(vlp_program* prog) {
 
 static vlp_status run_level(vlp_ctx* ctx, vlp_program* prog, uint32_t L) {
   const Level& lv = prog->levels[L];
-  LAUNCHCHECK(ctx, launch_br(prog->br_items + lv.br_first, lv.br_count, ctx->tw_fwd, ctx->tw_inv,
-                             ctx->tune.br_waves_per_block, (uint32_t)br_blocks(ctx), ctx->stream));
-  LAUNCHCHECK(ctx, launch_ks_group(prog->ks_items + lv.ks_first, lv.ks_count, prog->ks->ksk,
-                                   ctx->tune.ks_gates_per_block, ctx->stream));
+  LAUNCHCHECK(ctx, timed_br(ctx, prog->br_items + lv.br_first, lv.br_count));
+  LAUNCHCHECK(ctx, timed_ks(ctx, prog->ks_items + lv.ks_first, lv.ks_count, prog->ks->ksk));
   return VLP_OK;
 }
 
@@ -688,14 +748,12 @@ extern "C" vlp_status vlp_step(vlp_ctx* ctx, vlp_program* const* progs, size_t n
       ob += lv.br_count;
       ok += lv.ks_count;
     }
-    LAUNCHCHECK(ctx, launch_br(bri, (uint32_t)nbr, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
-                               (uint32_t)br_blocks(ctx), ctx->stream));
+    LAUNCHCHECK(ctx, timed_br(ctx, bri, (uint32_t)nbr));
     size_t gi = 0;
     for (size_t p = 0; p < n; ++p) {
       vlp_program* pr = progs[p];
       if (pr->next_level >= pr->levels.size()) continue;
-      LAUNCHCHECK(ctx, launch_ks_group(ksi + ks_groups[gi].first, (uint32_t)ks_groups[gi].second, pr->ks->ksk,
-                                       ctx->tune.ks_gates_per_block, ctx->stream));
+      LAUNCHCHECK(ctx, timed_ks(ctx, ksi + ks_groups[gi].first, (uint32_t)ks_groups[gi].second, pr->ks->ksk));
       gi++;
     }
   }
@@ -775,4 +833,30 @@ extern "C" vlp_status vlp_evaluate(vlp_ctx* ctx, const vlp_keyset* ks, const vlp
   }
   prog->next_level = 0;
   return vlp_program_run(ctx, prog, 1);
+}
+
+extern "C" vlp_status vlp_profile_enable(vlp_ctx* ctx, int enable) {
+  if (!ctx) return VLP_EINVAL;
+  ctx->prof = enable != 0;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_profile_read(vlp_ctx* ctx, vlp_kernel_stats* br, vlp_kernel_stats* ks) {
+  if (!ctx) return VLP_EINVAL;
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+  vlp_kernel_stats acc[2] = {{0, 0, 0.0}, {0, 0, 0.0}};
+  for (const auto& m : ctx->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.e0, m.e1) == hipSuccess) {
+      acc[m.kind].launches++;
+      acc[m.kind].items += m.items;
+      acc[m.kind].ms += ms;
+    }
+    ctx->event_pool.push_back(m.e0);
+    ctx->event_pool.push_back(m.e1);
+  }
+  ctx->marks.clear();
+  if (br) *br = acc[0];
+  if (ks) *ks = acc[1];
+  return VLP_OK;
 }

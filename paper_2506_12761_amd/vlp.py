@@ -32,6 +32,7 @@ EXPORTS = [
     "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_evaluate",
     "vlp_program_create", "vlp_program_reset", "vlp_step", "vlp_program_run", "vlp_program_counts",
     "vlp_plan_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
+    "vlp_profile_enable", "vlp_profile_read",
 ]
 
 
@@ -48,6 +49,10 @@ class vlp_params(ctypes.Structure):
 class vlp_shape(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("M", ctypes.c_uint32), ("l_I", ctypes.c_uint32),
                 ("l_S", ctypes.c_uint32), ("d", ctypes.c_uint32), ("optimized", ctypes.c_uint32)]
+
+
+class vlp_kernel_stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("items", ctypes.c_uint64), ("ms", ctypes.c_double)]
 
 
 class vlp_tuning(ctypes.Structure):
@@ -90,6 +95,8 @@ def lib():
             "vlp_get_tuning": (ctypes.c_int, [vp, P(vlp_tuning)]),
             "vlp_set_tuning": (ctypes.c_int, [vp, P(vlp_tuning)]),
             "vlp_sync": (ctypes.c_int, [vp]),
+            "vlp_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+            "vlp_profile_read": (ctypes.c_int, [vp, P(vlp_kernel_stats), P(vlp_kernel_stats)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -241,6 +248,17 @@ def vlp_set_tuning(ctx, br_waves_per_block: int, br_blocks_per_cu: int, ks_gates
 
 def vlp_sync(ctx) -> None:
     _check(ctx, lib().vlp_sync(ctx))
+
+
+def vlp_profile_enable(ctx, enable: bool = True) -> None:
+    _check(ctx, lib().vlp_profile_enable(ctx, 1 if enable else 0))
+
+
+def vlp_profile_read(ctx) -> dict:
+    br, ks = vlp_kernel_stats(), vlp_kernel_stats()
+    _check(ctx, lib().vlp_profile_read(ctx, ctypes.byref(br), ctypes.byref(ks)))
+    return {"br": {"launches": br.launches, "items": br.items, "ms": br.ms},
+            "ks": {"launches": ks.launches, "items": ks.items, "ms": ks.ms}}
 
 
 # ---------------------------------------------------------------------------
