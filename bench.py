@@ -32,17 +32,34 @@ sys.path.insert(0, ROOT)
 # 6 forward + 2 inverse 1024-point transforms of 5,120 butterflies and
 # 12 x 1,024 pointwise products): 630 * (8 * 5120 + 12 * 1024).
 MODMUL_PER_BR = 630 * (8 * 5120 + 12 * 1024)  # 33,546,240
-# Integer VALU peak of MI355X: 256 CUs x 64 lanes/clock x 2.4 GHz, and the
-# VALU operations of one Goldilocks multiply-and-reduce on gfx950 (4 32x32->64
-# multiply-adds + 12 adds/selects for the 2^64 = 2^32 - 1 fold).
+# Integer VALU peak of MI355X: 256 CUs x 64 lanes/clock x 2.4 GHz, divided by
+# the VALU operations of one exact multiplication modulo a 64-bit prime on
+# gfx950 (Goldilocks: 4 32x32->64 multiply-adds + 12 adds/selects for the
+# 2^64 = 2^32 - 1 fold), the reference modular-multiplication cost.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 OPS_PER_MODMUL = 16
 PEAK_MODMUL = VALU_LANE_OPS / OPS_PER_MODMUL  # 2.4576e12 modmul/s
 
+# A workload is one or more programs run together (their levels merged).
 WORKLOADS = {
-    "intv-1024": dict(mode="intv", M=1024, l=16, lS=0, d=2,
-                      label="interval validation, 1024 records, 16-bit 2-D boxes"),
+    "intv-1024": dict(label="interval validation, 1024 records, 16-bit 2-D boxes",
+                      programs=[dict(mode="intv", M=1024, l=16, lS=0, d=2)]),
+    # 4,096 cells, each an equality cell (CoV, depth 7) or a range cell (IntV,
+    # depth 23) by a seeded fair coin; both kinds share every launch.
+    "mixed-4096": dict(label="4096 20-bit cells, equality or range per cell (seeded coin)",
+                       programs="mixed"),
+    "idm-65536": dict(label="identifier match, 65536 records, 32-bit ids, 64-bit payload selection + XOR tree",
+                      programs=[dict(mode="idm", M=65536, l=32, lS=64, d=1)]),
+    "interval-8bit": dict(label="one 8-bit value against one interval (49 bootstraps)",
+                          programs=[dict(mode="intv", M=1, l=8, lS=0, d=1)]),
 }
+
+
+def mixed_programs(cells=4096, seed=0x5EED0003):
+    from paper_2506_12761_amd import synth
+    coin = synth.bits(synth.stream(seed, "cell_kind"), (cells,))
+    n_eq = int(coin.sum())
+    return [dict(mode="cov", M=n_eq, l=20, lS=0, d=2), dict(mode="intv", M=cells - n_eq, l=20, lS=0, d=2)]
 
 
 def log(*a):
@@ -89,6 +106,72 @@ def cpu_baseline(seconds: float, threads: int):
                       "%d threads, %.1f s wall" % (total, threads, el)}
 
 
+def serve_bench(args):
+    """Poisson stream of PIR queries, modes uniform over {IntV 16-bit, CoV 20-bit,
+    IdM 32-bit}, records log-uniform in [min, max], 64 payload bits, one of
+    `clients` key sets each; reports latency percentiles and queries/s."""
+    import numpy as np
+    import torch
+
+    from paper_2506_12761_amd import synth, vlp
+    from paper_2506_12761_amd.serve import GpuExecutor, Request, poisson_arrivals, serve
+    ctx = vlp.Context(0)
+    keysets = {}
+    for c in range(args.clients):
+        bk, ksk = synth.uniform_keys(0x5EED0005 + c)
+        keysets[c] = ctx.load_keys(bk, ksk)
+    g = synth.stream(0x5EED0005, "serve")
+    kinds = [("intv", 16, 2), ("cov", 20, 2), ("idm", 32, 1)]
+    reqs = []
+    for rid in range(args.requests):
+        mode, l, d = kinds[int(g.integers(0, 3))]
+        M = int(2 ** g.uniform(np.log2(args.min_records), np.log2(args.max_records)))
+        reqs.append(Request(rid, int(g.integers(0, args.clients)), mode, M, l, 64, d, arrival=0.0))
+    # Saturated rate estimate: blind rotations per query against a calibration run.
+    def plan_br(r):
+        return vlp.vlp_plan_counts(vlp.make_shape(r.mode, r.M, r.l_I, r.l_S, r.d))["blind_rotations"]
+    cal = Request(-1, 0, "intv", 256, 16, 0, 2, arrival=0.0)
+    q = ctx.tensor(synth.uniform_ciphertexts(1, "cq", (2, 16)))
+    loc = ctx.tensor(synth.uniform_ciphertexts(1, "cl", (256, 2, 2, 16)))
+    v = ctx.empty(256, 631)
+    sh = vlp.make_shape("intv", 256, 16, 0, 2)
+    vlp.vlp_evaluate(ctx.ctx, keysets[0], sh, q, loc, None, None, v)
+    ctx.sync()
+    t0 = time.perf_counter()
+    vlp.vlp_evaluate(ctx.ctx, keysets[0], sh, q, loc, None, None, v)
+    ctx.sync()
+    br_rate = plan_br(cal) / (time.perf_counter() - t0)
+    mean_br = sum(plan_br(r) for r in reqs) / len(reqs)
+    rate = args.load * br_rate / mean_br
+    arrivals = poisson_arrivals(rate, len(reqs), g)
+    for r, t in zip(reqs, arrivals):
+        r.arrival = t
+        shp = (r.d, r.l_I) if r.mode != "idm" else (r.l_I,)
+        lshape = {"intv": (r.M, r.d, 2, r.l_I), "cov": (r.M, r.d, r.l_I), "idm": (r.M, r.l_I)}[r.mode]
+        r.payload = {"query": ctx.tensor(synth.uniform_ciphertexts(r.rid, "q", shp)),
+                     "db_loc": ctx.tensor(synth.uniform_ciphertexts(r.rid, "l", lshape)),
+                     "db_pay": ctx.tensor(synth.uniform_ciphertexts(r.rid, "p", (r.M, 64))),
+                     "R": ctx.empty(64, 631), "v": ctx.empty(r.M, 631)}
+    log("serving %d requests, rate %.4f/s (load %.2f of %.0f bootstraps/s)" % (len(reqs), rate, args.load, br_rate))
+    torch.cuda.synchronize()
+    st = serve(reqs, GpuExecutor(ctx, keysets), log=log)
+    total_br = sum(plan_br(r) for r in st["requests"])
+    out = {
+        "metric": "PIR query latency under Poisson load (continuous batching), 1 GPU",
+        "value": st["p50_ms"], "unit": "ms (p50)", "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "higher_is_better": False, "queries_per_s": st["queries_per_s"],
+        "bootstraps_per_s_during_serving": total_br / st["wall_s"], "n_gpus": 1,
+        "queries": st["queries"], "steps": st["steps"], "max_active": st["max_active"],
+        "budget_rejections": st["budget_rejections"], "arrival_rate_per_s": rate, "load": args.load,
+        "calibrated_bootstraps_per_s": br_rate, "dtype": "u32", "data": "synthetic (seeded uniform keys and ciphertexts)",
+        "config": {"workload": "serving: modes uniform over IntV-16/CoV-20/IdM-32, records log-uniform "
+                               "%d..%d, 64 payload bits, %d clients" % (args.min_records, args.max_records, args.clients),
+                   "per_request": [(r.mode, r.M, round(r.latency * 1e3, 1)) for r in st["requests"]]},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,12 +183,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the level sequence as a HIP graph "
                     "(disables per-launch timing)")
+    ap.add_argument("--records", type=int, default=0, help="override the record count of every program")
+    ap.add_argument("--tuned", action="store_true", help="apply the cached autotuner result")
+    ap.add_argument("--serve", action="store_true", help="run the serving experiment instead")
+    ap.add_argument("--requests", type=int, default=12)
+    ap.add_argument("--clients", type=int, default=3)
+    ap.add_argument("--min-records", type=int, default=256)
+    ap.add_argument("--max-records", type=int, default=2048)
+    ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(records would shard across GPUs; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return serve_bench(args)
 
     import numpy as np
     import torch
@@ -113,31 +206,46 @@ def main():
     from paper_2506_12761_amd import synth, vlp
     assert torch.cuda.is_available(), "no HIP device"
     wl = WORKLOADS[args.workload]
-    mode, M, l, lS, d = wl["mode"], wl["M"], wl["l"], wl["lS"], wl["d"]
+    specs = mixed_programs() if wl["programs"] == "mixed" else [dict(p) for p in wl["programs"]]
+    if args.records:
+        for p in specs:
+            p["M"] = args.records
 
     log("generating synthetic keys and ciphertexts ...")
     bk, ksk = synth.uniform_keys(0x5EED0002)
-    q_shape = (d, l) if mode != "idm" else (l,)
-    loc_shape = {"intv": (M, d, 2, l), "cov": (M, d, l), "idm": (M, l)}[mode]
-    query = synth.uniform_ciphertexts(0x5EED0002, "query", q_shape)
-    db_loc = synth.uniform_ciphertexts(0x5EED0002, "db_loc", loc_shape)
-    db_pay = synth.uniform_ciphertexts(0x5EED0002, "db_pay", (M, lS)) if lS else None
-
     ctx = vlp.Context(0)
     ks = ctx.load_keys(bk, ksk)
-    d_q, d_loc = ctx.tensor(query), ctx.tensor(db_loc)
-    d_pay = ctx.tensor(db_pay) if lS else None
-    d_R = ctx.empty(lS, 631) if lS else None
-    d_v = ctx.empty(M, 631)
-    shape = vlp.make_shape(mode, M, l, lS, d)
-    prog = vlp.vlp_program_create(ctx.ctx, ks, shape, d_q, d_loc, d_pay, d_R, d_v)
-    counts = vlp.vlp_program_counts(ctx.ctx, prog)
-    br_step, ks_step = counts["blind_rotations"], counts["key_switches"]
-    log("program: %s" % counts)
+    if args.tuned:
+        from paper_2506_12761_amd import autotune
+        log("cached tuning applied: %s" % autotune.load_cached(ctx, args.workload))
+    progs, keep = [], []
+    for k, p in enumerate(specs):
+        mode, M, l, lS, d = p["mode"], p["M"], p["l"], p["lS"], p["d"]
+        q_shape = (d, l) if mode != "idm" else (l,)
+        loc_shape = {"intv": (M, d, 2, l), "cov": (M, d, l), "idm": (M, l)}[mode]
+        d_q = ctx.tensor(synth.uniform_ciphertexts(0x5EED0002, "query%d" % k, q_shape))
+        d_loc = ctx.tensor(synth.uniform_ciphertexts(0x5EED0002, "db_loc%d" % k, loc_shape))
+        d_pay = ctx.tensor(synth.uniform_ciphertexts(0x5EED0002, "db_pay%d" % k, (M, lS))) if lS else None
+        d_R = ctx.empty(lS, 631) if lS else None
+        d_v = ctx.empty(M, 631)
+        keep.append((d_q, d_loc, d_pay, d_R, d_v))
+        progs.append(vlp.vlp_program_create(ctx.ctx, ks, vlp.make_shape(mode, M, l, lS, d), d_q, d_loc, d_pay,
+                                            d_R, d_v))
+    counts = [vlp.vlp_program_counts(ctx.ctx, pr) for pr in progs]
+    br_step = sum(c["blind_rotations"] for c in counts)
+    ks_step = sum(c["key_switches"] for c in counts)
+    gates_step = sum(c["gates"] for c in counts)
+    levels = max(c["levels"] for c in counts)
+    log("programs: %s" % counts)
 
     def step():
-        vlp.vlp_program_reset(ctx.ctx, prog)
-        vlp.vlp_program_run(ctx.ctx, prog, use_graph=args.graph)
+        for pr in progs:
+            vlp.vlp_program_reset(ctx.ctx, pr)
+        if len(progs) == 1:
+            vlp.vlp_program_run(ctx.ctx, progs[0], use_graph=args.graph)
+        else:
+            while vlp.vlp_step(ctx.ctx, progs):
+                pass
 
     for _ in range(args.warmup):
         step()
@@ -207,12 +315,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "u32",
         "data": "synthetic (seeded uniform keys and ciphertexts)",
-        "config": {"workload": wl["label"], "records": M, "l_I": l, "d": d, "l_S": lS,
+        "config": {"workload": wl["label"], "programs": specs,
                    "blind_rotations_per_step": br_step, "key_switches_per_step": ks_step,
-                   "levels": counts["levels"], "graph": bool(args.graph)},
-        "gates_per_s": counts["gates"] * args.steps / elapsed,
+                   "levels": levels, "graph": bool(args.graph)},
+        "gates_per_s": gates_step * args.steps / elapsed,
         "key_switches_per_s": ks_step * args.steps / elapsed,
         "plain_bootstraps_per_s": plain_rate,
         "speedup_batched_vs_plain": value / plain_rate,
@@ -221,7 +329,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    vlp.vlp_program_destroy(ctx.ctx, prog)
+    for pr in progs:
+        vlp.vlp_program_destroy(ctx.ctx, pr)
     ctx.close()
 
 

@@ -189,7 +189,7 @@ vlp_status vlp_program_counts(const vlp_program *prog, uint64_t *gates, uint64_t
 vlp_status vlp_program_destroy(vlp_program *prog);
 
 /* ---- Tuning knobs of the batched kernels (picked by the autotuner).
- * br_waves_per_block: waves per workgroup of the blind-rotation kernel (1, 2, 4, 8)
+ * br_waves_per_block: waves per workgroup of the blind-rotation kernel (1, 2, 4)
  * br_blocks_per_cu  : resident workgroups per compute unit the grid is sized for
  * ks_gates_per_block: gates sharing one pass over the key-switching key */
 typedef struct {

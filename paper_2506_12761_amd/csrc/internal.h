@@ -3,6 +3,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <hip/hip_runtime.h>
+
 namespace vlp {
 
 constexpr int LWE_n = 630;          // LWE dimension (Table 5)
@@ -16,10 +18,11 @@ constexpr int CT_N = RING_N + 1;    // words of an LWE_N ciphertext
 constexpr int KS_ROW = 640;         // padded words per key-switching-key row (>= 631)
 constexpr uint32_t MU = 0x20000000u; // 1/8
 
-// Transformed bootstrapping key: [630][6 rows][2 components][1024] residues
-// mod p, each polynomial in the NTT's transform order (layout C, stored as
-// [r][lane] so a wave's loads are contiguous), scaled by 1/1024.
-constexpr size_t BK_NTT_WORDS = (size_t)LWE_n * 2 * ELL * 2 * RING_N;  // u64 words
+// Transformed bootstrapping key: [630][6 rows][2 components][1024] residue
+// pairs (mod P1, mod P2), each polynomial in the NTT's transform order
+// (layout C, stored as [r][lane] so a wave's loads are contiguous), scaled
+// by 1/1024 and kept in Montgomery form (times 2^32 mod P).
+constexpr size_t BK_NTT_WORDS = (size_t)LWE_n * 2 * ELL * 2 * RING_N;  // uint2 entries
 // Re-laid key-switching key: [1024][8][3 digits 1..3][640] words.
 constexpr size_t KSK_WORDS = (size_t)RING_N * KS_T * 3 * KS_ROW;       // u32 words
 
@@ -29,7 +32,7 @@ struct BrItem {
   const uint32_t* a;
   const uint32_t* b;    // may be null (then cb is ignored)
   uint32_t* out;        // [1025]
-  const uint64_t* bk;   // transformed bootstrapping key
+  const uint2* bk;      // transformed bootstrapping key
   int32_t ca, cb;
   uint32_t cst, mu;
 };
@@ -46,19 +49,21 @@ struct KsItem {
 
 // Host-side launchers (kernels.hip).  All enqueue on `stream` and return the
 // HIP error of the launch.
-int launch_bk_transform(const uint32_t* bk_coeff, uint64_t* bk_ntt, const uint64_t* tw_fwd, void* stream);
+int launch_bk_transform(const uint32_t* bk_coeff, uint2* bk_ntt, const uint4* tw_fwd, void* stream);
 int launch_ksk_relayout(const uint32_t* ksk_in, uint32_t* ksk_out, void* stream);
-int launch_br(const BrItem* items, uint32_t count, const uint64_t* tw_fwd, const uint64_t* tw_inv,
-              uint32_t waves_per_block, uint32_t blocks, void* stream);
+int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t waves_per_block, uint32_t blocks,
+              void* stream);
 int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream);
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
-                         uint32_t cst, uint32_t mu, uint32_t* out, const uint64_t* bk, void* stream);
+                         uint32_t cst, uint32_t mu, uint32_t* out, const uint2* bk, void* stream);
 int launch_make_ks_items(KsItem* items, uint32_t count, const uint32_t* u1, const uint32_t* u2, uint32_t cst,
                          uint32_t* out, const uint32_t* ksk, void* stream);
 int launch_negate(const uint32_t* a, uint32_t* out, size_t words, void* stream);
 
-// Twiddle tables (host): psi^brv10(m) and psi^-brv10(m), m < 1024, modulo
-// the Goldilocks prime, psi = 7^((p-1)/2048).
-void make_twiddles(uint64_t* tw_fwd, uint64_t* tw_inv);
+// Twiddle table (host), 4 words per m < 1024: {w1, Shoup(w1), w2, Shoup(w2)}
+// with w_k = psi_k^brv10(m) mod P_k (the inverse transform reads it too).
+void make_twiddles(uint32_t* tw);
+// Per prime {N^-1 2^32 mod P, its Shoup quotient}: the key's scale factor.
+void key_scale(uint32_t out[4]);
 
 }  // namespace vlp

@@ -2,8 +2,8 @@
 // sample extraction, batched key switching, and small helpers.
 #include <hip/hip_runtime.h>
 
-#include "gl64.h"
 #include "internal.h"
+#include "rns.h"
 #include "wave_ntt.h"
 
 namespace vlp {
@@ -13,27 +13,35 @@ namespace vlp {
 // ---------------------------------------------------------------------------
 
 // One wave per bootstrapping-key polynomial: residues of the coefficient words
-// (taken as integers in [0, 2^32)), forward transform, times 1/1024.
+// (integers in [0, 2^32)), forward transform, canonical, times the key scale
+// 2^32 / 1024 (mod P_k), canonical again.
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t* __restrict__ bk_coeff,
-                                                                   uint64_t* __restrict__ bk_ntt,
-                                                                   const uint64_t* __restrict__ tw_fwd,
-                                                                   uint32_t n_polys, uint64_t n_inv) {
-  __shared__ uint64_t s_tw[RING_N];
-  __shared__ uint64_t s_buf[WAVES][RING_N];
+                                                                   uint2* __restrict__ bk_ntt,
+                                                                   const Tw* __restrict__ tw_fwd,
+                                                                   uint32_t n_polys, uint4 scale) {
+  __shared__ Tw s_tw[RING_N];
+  __shared__ uint2 s_buf[WAVES][RING_N];
   for (int k = threadIdx.x; k < RING_N; k += blockDim.x) s_tw[k] = tw_fwd[k];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (uint32_t poly = blockIdx.x * WAVES + wave; poly < n_polys; poly += gridDim.x * WAVES) {
     const uint32_t* src = bk_coeff + (size_t)poly * RING_N;
-    uint64_t v[16];
+    Poly2 v;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = src[lay_a(lane, r)];
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t x = src[lay_a(lane, r)];
+      v.a[r] = x % P1;
+      v.b[r] = x % P2;
+    }
     ntt_fwd(v, s_buf[wave], s_tw, lane);
-    uint64_t* dst = bk_ntt + (size_t)poly * RING_N;
+    uint2* dst = bk_ntt + (size_t)poly * RING_N;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) dst[r * 64 + lane] = gl_canon(gl_mul(v[r], n_inv));
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t a = csub(csub(v.a[r], 2 * P1), P1), b = csub(csub(v.b[r], 2 * P2), P2);
+      dst[r * 64 + lane] = make_uint2(csub(shoup(a, scale.x, scale.y, P1), P1), csub(shoup(b, scale.z, scale.w, P2), P2));
+    }
   }
 }
 
@@ -53,22 +61,23 @@ __global__ void ksk_relayout_kernel(const uint32_t* __restrict__ in, uint32_t* _
 // ---------------------------------------------------------------------------
 constexpr uint32_t DEC_OFFSET = (1u << 31) + (1u << 24) + (1u << 17) + (1u << 10);
 
+// Global-address-space views: loads through them are global (not flat)
+// loads, so they are not counted by the LDS wait of the transposes.
+typedef const uint64_t __attribute__((address_space(1))) g_u64;
+typedef const uint32_t __attribute__((address_space(1))) g_u32;
+
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict__ items, uint32_t count,
-                                                         const uint64_t* __restrict__ tw_fwd,
-                                                         const uint64_t* __restrict__ tw_inv) {
-  __shared__ uint64_t s_tw[2][RING_N];            // forward / inverse twiddles
-  __shared__ uint64_t s_buf[WAVES][RING_N];       // transpose scratch, one per wave
-  __shared__ uint32_t s_acc[WAVES][2][RING_N];    // accumulator (A, B), coefficient order
-  __shared__ uint16_t s_abar[WAVES][CT_n + 1];    // modulus-switched input
-  for (int k = threadIdx.x; k < RING_N; k += blockDim.x) {
-    s_tw[0][k] = tw_fwd[k];
-    s_tw[1][k] = tw_inv[k];
-  }
+                                                         const Tw* __restrict__ tw_fwd) {
+  __shared__ Tw s_tw[RING_N];                   // twiddles of both primes (16 KB)
+  __shared__ uint2 s_buf[WAVES][RING_N];        // per-wave transpose scratch
+  __shared__ uint32_t s_acc[WAVES][2][RING_N];  // per-wave accumulator (A, B), coefficient order
+  __shared__ uint16_t s_abar[WAVES][CT_n + 1];  // modulus-switched input
+  for (int k = threadIdx.x; k < RING_N; k += blockDim.x) s_tw[k] = tw_fwd[k];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint64_t* buf = s_buf[wave];
+  uint2* buf = s_buf[wave];
   uint32_t* acc = s_acc[wave][0];
   uint16_t* abar = s_abar[wave];
 
@@ -76,14 +85,16 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
     const BrItem I = items[it];
     // Gate pre-combination and modulus switch of all 631 words.
     wave_lds_sync();
+    const g_u32* in_a = (const g_u32*)I.a;
+    const g_u32* in_b = (const g_u32*)I.b;
     for (int w = lane; w < CT_n; w += 64) {
-      uint32_t x = (uint32_t)I.ca * I.a[w];
-      if (I.b) x += (uint32_t)I.cb * I.b[w];
+      uint32_t x = (uint32_t)I.ca * in_a[w];
+      if (I.b) x += (uint32_t)I.cb * in_b[w];
       if (w == LWE_n) x += I.cst;
       abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
     }
     wave_lds_sync();
-    // acc = (0, X^(-bbar) * mu * (1 + X + ... + X^1023)).
+    // acc = (0, X^(-bbar) * mu * (1 + X + ... + X^1023)); coefficient j = 64 r + lane.
     const uint32_t bbar = __builtin_amdgcn_readfirstlane(abar[LWE_n]);
     const uint32_t rot = (2048u - bbar) & 2047u;
 #pragma unroll
@@ -93,49 +104,69 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
       acc[j] = 0;
       acc[RING_N + j] = neg ? (0u - I.mu) : I.mu;
     }
-    const uint64_t* bk_i = I.bk;
+    const uint2* bk_i = I.bk;
     for (int i = 0; i < LWE_n; ++i, bk_i += 2 * ELL * 2 * RING_N) {
       const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
       if (ab == 0) continue;
-      wave_lds_sync();  // accumulator updates of the previous step are visible
-      // External product BK_i x (X^ab acc - acc), accumulated in the transform domain.
-      uint64_t acc0[16], acc1[16];
+      // External product BK_i x (X^ab acc - acc): the six digit polynomials are
+      // transformed one at a time; each product with the key (Montgomery form)
+      // is reduced to [0, P) and summed lazily (six terms stay below 6P < 2^32).
+      uint32_t m0a[16], m0b[16], m1a[16], m1b[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
+      for (int r = 0; r < 16; ++r) m0a[r] = m0b[r] = m1a[r] = m1b[r] = 0;
+      wave_lds_sync();  // accumulator updates of the previous step are visible
 #pragma unroll 1
-      for (int row = 0; row < 2 * ELL; ++row) {
-        const int c = row < ELL ? 0 : 1;
-        const int lev = row - c * ELL;
-        const int shift = 32 - BG_BIT * (lev + 1);
+      for (int c = 0; c < 2; ++c) {
         const uint32_t* poly = acc + c * RING_N;
-        uint64_t v[16];
+        uint32_t D[16];  // X^ab p - p, plus the rounding offset of the decomposition
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t j = r * 64 + lane;
-          const uint32_t s = (j + 2048u - ab) & 2047u;  // X^ab: coefficient j comes from j - ab
+          const uint32_t s = (j + 2048u - ab) & 2047u;  // coefficient j of X^ab p is +-p[j - ab]
           const uint32_t src = poly[s & 1023u];
-          const uint32_t dj = (s >= 1024u ? 0u - src : src) - poly[j];
-          const int32_t d = (int32_t)(((dj + DEC_OFFSET) >> shift) & 127u) - 64;
-          v[r] = gl_from_i32(d);
+          D[r] = (s >= 1024u ? 0u - src : src) - poly[j] + DEC_OFFSET;
         }
-        ntt_fwd(v, buf, s_tw[0], lane);
-        const uint64_t* k0 = bk_i + (size_t)(row * 2) * RING_N;
-        const uint64_t* k1 = k0 + RING_N;
+#pragma unroll 1
+        for (int lev = 0; lev < ELL; ++lev) {
+          // This row's key words are requested first; the transform hides their latency.
+          const g_u64* k0 = (const g_u64*)(bk_i + (size_t)((c * ELL + lev) * 2) * RING_N);
+          uint64_t b0[16], b1[16];  // {residue mod P1 (low word), residue mod P2 (high word)}
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          acc0[r] = gl_add_wc(acc0[r], gl_canon(gl_mul(v[r], k0[r * 64 + lane])));
-          acc1[r] = gl_add_wc(acc1[r], gl_canon(gl_mul(v[r], k1[r * 64 + lane])));
+          for (int r = 0; r < 16; ++r) {
+            b0[r] = k0[r * 64 + lane];
+            b1[r] = k0[RING_N + r * 64 + lane];
+          }
+          const int shift = 32 - BG_BIT * (lev + 1);
+          Poly2 v;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int32_t d = (int32_t)((D[r] >> shift) & 127u) - 64;
+            v.a[r] = res_of(d, P1);
+            v.b[r] = res_of(d, P2);
+          }
+          ntt_fwd(v, buf, s_tw, lane);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const uint32_t da = csub(v.a[r], 2 * P1), db = csub(v.b[r], 2 * P2);  // [0, 2P)
+            m0a[r] += redc((uint64_t)da * (uint32_t)b0[r], P1, P1_INV);
+            m0b[r] += redc((uint64_t)db * (uint32_t)(b0[r] >> 32), P2, P2_INV);
+            m1a[r] += redc((uint64_t)da * (uint32_t)b1[r], P1, P1_INV);
+            m1b[r] += redc((uint64_t)db * (uint32_t)(b1[r] >> 32), P2, P2_INV);
+          }
         }
       }
 #pragma unroll 1
       for (int c = 0; c < 2; ++c) {
-        uint64_t v[16];
+        Poly2 v;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = c ? acc1[r] : acc0[r];
-        ntt_inv(v, buf, s_tw[1], lane);
+        for (int r = 0; r < 16; ++r) {  // [0, 6P) -> [0, 2P)
+          v.a[r] = csub(csub(c ? m1a[r] : m0a[r], 4 * P1), 2 * P1);
+          v.b[r] = csub(csub(c ? m1b[r] : m0b[r], 4 * P2), 2 * P2);
+        }
+        ntt_inv(v, buf, s_tw, lane);
         uint32_t* poly = acc + c * RING_N;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) poly[r * 64 + lane] += gl_lift_u32(v[r]);
+        for (int r = 0; r < 16; ++r) poly[r * 64 + lane] += crt_lift_u32(csub(v.a[r], P1), csub(v.b[r], P2));
       }
     }
     wave_lds_sync();
@@ -220,7 +251,7 @@ __global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict
 // Helpers
 // ---------------------------------------------------------------------------
 __global__ void make_br_items_kernel(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca,
-                                     int32_t cb, uint32_t cst, uint32_t mu, uint32_t* out, const uint64_t* bk) {
+                                     int32_t cb, uint32_t cst, uint32_t mu, uint32_t* out, const uint2* bk) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   BrItem it;
@@ -259,12 +290,13 @@ __global__ void negate_kernel(const uint32_t* a, uint32_t* out, size_t words) {
 // ---------------------------------------------------------------------------
 static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-int launch_bk_transform(const uint32_t* bk_coeff, uint64_t* bk_ntt, const uint64_t* tw_fwd, void* stream) {
+int launch_bk_transform(const uint32_t* bk_coeff, uint2* bk_ntt, const uint4* tw_fwd, void* stream) {
   const uint32_t n_polys = LWE_n * 2 * ELL * 2;
-  // 1/1024 mod p = p - (p - 1) / 1024
-  const uint64_t n_inv = GL_P - (GL_P - 1) / RING_N;
+  uint32_t sc[4];
+  key_scale(sc);
+  const uint4 scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
   hipLaunchKernelGGL(bk_transform_kernel<4>, dim3((n_polys + 3) / 4), dim3(256), 0, S(stream), bk_coeff, bk_ntt, tw_fwd,
-                     n_polys, n_inv);
+                     n_polys, scale);
   return (int)hipGetLastError();
 }
 
@@ -273,16 +305,15 @@ int launch_ksk_relayout(const uint32_t* ksk_in, uint32_t* ksk_out, void* stream)
   return (int)hipGetLastError();
 }
 
-int launch_br(const BrItem* items, uint32_t count, const uint64_t* tw_fwd, const uint64_t* tw_inv,
-              uint32_t waves_per_block, uint32_t blocks, void* stream) {
+int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t waves_per_block, uint32_t blocks,
+              void* stream) {
   if (count == 0) return 0;
   const uint32_t need = (count + waves_per_block - 1) / waves_per_block;
   if (blocks == 0 || blocks > need) blocks = need;
   switch (waves_per_block) {
-    case 1: hipLaunchKernelGGL(br_kernel<1>, dim3(blocks), dim3(64), 0, S(stream), items, count, tw_fwd, tw_inv); break;
-    case 2: hipLaunchKernelGGL(br_kernel<2>, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd, tw_inv); break;
-    case 4: hipLaunchKernelGGL(br_kernel<4>, dim3(blocks), dim3(256), 0, S(stream), items, count, tw_fwd, tw_inv); break;
-    case 8: hipLaunchKernelGGL(br_kernel<8>, dim3(blocks), dim3(512), 0, S(stream), items, count, tw_fwd, tw_inv); break;
+    case 1: hipLaunchKernelGGL(br_kernel<1>, dim3(blocks), dim3(64), 0, S(stream), items, count, tw_fwd); break;
+    case 2: hipLaunchKernelGGL(br_kernel<2>, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd); break;
+    case 4: hipLaunchKernelGGL(br_kernel<4>, dim3(blocks), dim3(256), 0, S(stream), items, count, tw_fwd); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
@@ -306,7 +337,7 @@ int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, ui
 }
 
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
-                         uint32_t cst, uint32_t mu, uint32_t* out, const uint64_t* bk, void* stream) {
+                         uint32_t cst, uint32_t mu, uint32_t* out, const uint2* bk, void* stream) {
   if (count == 0) return 0;
   hipLaunchKernelGGL(make_br_items_kernel, dim3((count + 255) / 256), dim3(256), 0, S(stream), items, count, a, b, ca,
                      cb, cst, mu, out, bk);

@@ -1,24 +1,13 @@
-// Host-side twiddle tables for the wave NTT modulo the Goldilocks prime.
+// Host-side twiddle tables for the two-prime wave NTT.
 #include <stdint.h>
 
+#include <vector>
+
 #include "internal.h"
+#include "rns.h"
 
 namespace vlp {
 namespace {
-
-constexpr uint64_t P = 0xFFFFFFFF00000001ull;
-
-uint64_t mulmod(uint64_t a, uint64_t b) { return (uint64_t)((unsigned __int128)a * b % P); }
-
-uint64_t powmod(uint64_t b, uint64_t e) {
-  uint64_t r = 1;
-  while (e) {
-    if (e & 1) r = mulmod(r, b);
-    b = mulmod(b, b);
-    e >>= 1;
-  }
-  return r;
-}
 
 uint32_t brv10(uint32_t x) {
   uint32_t r = 0;
@@ -26,15 +15,46 @@ uint32_t brv10(uint32_t x) {
   return r;
 }
 
+// Smallest generator of the multiplicative group mod the prime p.
+uint64_t generator(uint64_t p) {
+  std::vector<uint64_t> f;
+  uint64_t n = p - 1;
+  for (uint64_t d = 2; d * d <= n; ++d)
+    if (n % d == 0) {
+      f.push_back(d);
+      while (n % d == 0) n /= d;
+    }
+  if (n > 1) f.push_back(n);
+  for (uint64_t g = 2;; ++g) {
+    bool ok = true;
+    for (uint64_t q : f) ok = ok && pow_mod(g, (p - 1) / q, p) != 1;
+    if (ok) return g;
+  }
+}
+
 }  // namespace
 
-void make_twiddles(uint64_t* tw_fwd, uint64_t* tw_inv) {
-  // 7 generates the multiplicative group mod p, so 7^((p-1)/2048) has order 2048.
-  const uint64_t psi = powmod(7, (P - 1) / 2048);
-  const uint64_t psi_inv = powmod(psi, P - 2);
-  for (uint32_t m = 0; m < (uint32_t)RING_N; ++m) {
-    tw_fwd[m] = powmod(psi, brv10(m));
-    tw_inv[m] = powmod(psi_inv, brv10(m));
+void make_twiddles(uint32_t* tw) {
+  const uint32_t primes[2] = {P1, P2};
+  for (int k = 0; k < 2; ++k) {
+    const uint64_t p = primes[k];
+    const uint64_t psi = pow_mod(generator(p), (p - 1) / 2048, p);  // order 2048
+    for (uint32_t m = 0; m < (uint32_t)RING_N; ++m) {
+      const uint64_t w = pow_mod(psi, brv10(m), p);
+      tw[4 * m + 2 * k] = (uint32_t)w;
+      tw[4 * m + 2 * k + 1] = (uint32_t)((w << 32) / p);
+    }
+  }
+}
+
+// Per prime: N^-1 * 2^32 mod p (Montgomery form of 1/1024) and its Shoup quotient.
+void key_scale(uint32_t out[4]) {
+  const uint32_t primes[2] = {P1, P2};
+  for (int k = 0; k < 2; ++k) {
+    const uint64_t p = primes[k];
+    const uint64_t v = pow_mod(RING_N, p - 2, p) * ((1ull << 32) % p) % p;
+    out[2 * k] = (uint32_t)v;
+    out[2 * k + 1] = (uint32_t)((v << 32) / p);
   }
 }
 

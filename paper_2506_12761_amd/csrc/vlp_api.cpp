@@ -22,10 +22,9 @@ struct vlp_ctx {
   bool own_stream = false;
   size_t budget = 0, used = 0;
   std::string err;
-  uint64_t* tw_fwd = nullptr;  // device twiddle tables
-  uint64_t* tw_inv = nullptr;
+  uint4* tw_fwd = nullptr;  // device twiddle table
   int num_cus = 256;
-  vlp_tuning tune{2, 3, 8};
+  vlp_tuning tune{4, 1, 8};
   // Grow-only scratch for the elementwise calls.
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -40,7 +39,7 @@ struct vlp_ctx {
 
 struct vlp_keyset {
   vlp_ctx* ctx;
-  uint64_t* bk_ntt;
+  uint2* bk_ntt;
   uint32_t* ksk;
   int users;  // live programs made with it
 };
@@ -150,8 +149,8 @@ void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
 int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
   if (count == 0) return 0;
   const int m = mark_begin(ctx);
-  const int e = launch_br(items, count, ctx->tw_fwd, ctx->tw_inv, ctx->tune.br_waves_per_block,
-                          (uint32_t)br_blocks(ctx), ctx->stream);
+  const int e = launch_br(items, count, ctx->tw_fwd, ctx->tune.br_waves_per_block, (uint32_t)br_blocks(ctx),
+                          ctx->stream);
   mark_end(ctx, m, 0, count);
   return e;
 }
@@ -217,7 +216,7 @@ uint32_t encode_bit(uint32_t bit) { return bit ? MU : 0u - MU; }
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
-extern "C" const char* vlp_version(void) { return "vlp 0.1 (gfx950, Goldilocks NTT)"; }
+extern "C" const char* vlp_version(void) { return "vlp 0.2 (gfx950, two-prime NTT)"; }
 
 extern "C" void vlp_default_params(vlp_params* p) {
   if (!p) return;
@@ -273,19 +272,16 @@ extern "C" vlp_status vlp_ctx_create(vlp_ctx** out, const vlp_params* p, int dev
     delete ctx;
     return VLP_EHIP;
   }
-  std::vector<uint64_t> tf(RING_N), ti(RING_N);
-  make_twiddles(tf.data(), ti.data());
-  vlp_status st = dev_alloc(ctx, (void**)&ctx->tw_fwd, RING_N * 8);
-  if (st == VLP_OK) st = dev_alloc(ctx, (void**)&ctx->tw_inv, RING_N * 8);
+  std::vector<uint32_t> tf(4 * RING_N);
+  make_twiddles(tf.data());
+  vlp_status st = dev_alloc(ctx, (void**)&ctx->tw_fwd, RING_N * 16);
   if (st == VLP_OK) {
-    e = hipMemcpy(ctx->tw_fwd, tf.data(), RING_N * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ctx->tw_inv, ti.data(), RING_N * 8, hipMemcpyHostToDevice);
+    e = hipMemcpy(ctx->tw_fwd, tf.data(), RING_N * 16, hipMemcpyHostToDevice);
     if (e != hipSuccess) st = fail(ctx, VLP_EHIP, "twiddle upload: %s", hipGetErrorString(e));
   }
   if (st != VLP_OK) {
     g_create_err = ctx->err;
-    dev_free(ctx, ctx->tw_fwd, RING_N * 8);
-    dev_free(ctx, ctx->tw_inv, RING_N * 8);
+    dev_free(ctx, ctx->tw_fwd, RING_N * 16);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return st;
@@ -309,8 +305,7 @@ extern "C" vlp_status vlp_ctx_destroy(vlp_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   dev_free(ctx, ctx->scratch, ctx->scratch_bytes);
-  dev_free(ctx, ctx->tw_fwd, RING_N * 8);
-  dev_free(ctx, ctx->tw_inv, RING_N * 8);
+  dev_free(ctx, ctx->tw_fwd, RING_N * 16);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return VLP_OK;
@@ -338,7 +333,7 @@ extern "C" vlp_status vlp_get_tuning(const vlp_ctx* ctx, vlp_tuning* t) {
 extern "C" vlp_status vlp_set_tuning(vlp_ctx* ctx, const vlp_tuning* t) {
   if (!ctx || !t) return VLP_EINVAL;
   const uint32_t w = t->br_waves_per_block, g = t->ks_gates_per_block;
-  if (!(w == 1 || w == 2 || w == 4 || w == 8)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2, 4 or 8");
+  if (!(w == 1 || w == 2 || w == 4)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2 or 4");
   if (t->br_blocks_per_cu < 1 || t->br_blocks_per_cu > 64) return fail(ctx, VLP_EINVAL, "br_blocks_per_cu out of [1, 64]");
   if (!(g == 4 || g == 8 || g == 16)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 4, 8 or 16");
   ctx->tune = *t;

@@ -1,0 +1,188 @@
+"""Continuous-batching server for PIR queries over the bootstrapping library.
+
+Requests arrive over time, each a full VeLoPIR query (Algorithm 3) of one
+client against that client's encrypted database, in one of the three modes.
+The loop keeps every client's keys resident, admits a request when its
+program (gate schedule plus intermediate ciphertexts) fits the device-memory
+budget, and advances all admitted requests together: every step runs the
+current circuit level of every active request in one merged batch of kernel
+launches, so a request admitted while others are running joins at the next
+step, and finished requests free their memory for queued ones.
+
+The executor is an interface so the scheduling logic can be exercised on a
+CPU with a stand-in executor; GpuExecutor drives libvlp.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+
+class BudgetExceeded(Exception):
+    """The executor cannot hold the request's program right now."""
+
+
+@dataclass
+class Request:
+    rid: int
+    client: int
+    mode: str
+    M: int
+    l_I: int
+    l_S: int
+    d: int
+    arrival: float                # seconds since the start of the run
+    payload: dict = field(default_factory=dict)  # executor-specific buffers
+    admitted: float | None = None
+    finished: float | None = None
+    handle: object = None
+
+    @property
+    def latency(self) -> float | None:
+        return None if self.finished is None else self.finished - self.arrival
+
+
+class Executor:
+    """What the server needs from a backend."""
+
+    def create(self, req: Request):            # -> handle; raises BudgetExceeded
+        raise NotImplementedError
+
+    def step(self, handles: list) -> None:     # advance each unfinished handle by one level, wait for it
+        raise NotImplementedError
+
+    def levels_left(self, handle) -> int:
+        raise NotImplementedError
+
+    def destroy(self, handle) -> None:
+        raise NotImplementedError
+
+
+class GpuExecutor(Executor):
+    """libvlp programs on one device; keysets[client] must already be loaded."""
+
+    def __init__(self, ctx, keysets: dict):
+        from . import vlp
+        self.vlp = vlp
+        self.ctx = ctx
+        self.keysets = keysets
+        self._left = {}
+
+    def create(self, req: Request):
+        v = self.vlp
+        p = req.payload
+        shape = v.make_shape(req.mode, req.M, req.l_I, req.l_S, req.d)
+        try:
+            h = v.vlp_program_create(self.ctx.ctx, self.keysets[req.client], shape, p["query"], p["db_loc"],
+                                     p.get("db_pay"), p.get("R"), p.get("v"))
+        except v.VlpError as e:
+            if e.status == v.VLP_EBUDGET:
+                raise BudgetExceeded(str(e)) from None
+            raise
+        self._left[h] = v.vlp_program_counts(self.ctx.ctx, h)["levels"]
+        return h
+
+    def step(self, handles):
+        if not handles:
+            return
+        self.vlp.vlp_step(self.ctx.ctx, handles)
+        self.vlp.vlp_sync(self.ctx.ctx)
+        for h in handles:
+            if self._left[h] > 0:
+                self._left[h] -= 1
+
+    def levels_left(self, handle) -> int:
+        return self._left[handle]
+
+    def destroy(self, handle):
+        self._left.pop(handle, None)
+        self.vlp.vlp_program_destroy(self.ctx.ctx, handle)
+
+
+def serve(requests: list[Request], executor: Executor, max_active: int | None = None,
+          clock=time.perf_counter, sleep=time.sleep, log=None) -> dict:
+    """Run the request stream to completion; returns latency statistics.
+
+    Arrival times are offsets from the start.  A request is admitted at the
+    first step boundary after its arrival at which the executor accepts it
+    (arrival order, no overtaking); each step advances every admitted,
+    unfinished request by one circuit level."""
+    pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    waiting: list[Request] = []
+    active: list[Request] = []
+    done: list[Request] = []
+    t0 = clock()
+    steps = 0
+    max_active_seen = 0
+    rejected_attempts = 0
+    while pending or waiting or active:
+        now = clock() - t0
+        while pending and pending[0].arrival <= now:
+            waiting.append(pending.pop(0))
+        # Admission in arrival order while memory allows.
+        while waiting and (max_active is None or len(active) < max_active):
+            r = waiting[0]
+            try:
+                r.handle = executor.create(r)
+            except BudgetExceeded:
+                rejected_attempts += 1
+                break
+            r.admitted = clock() - t0
+            active.append(waiting.pop(0))
+        if not active:
+            if not waiting and pending:  # idle until the next arrival
+                sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+                continue
+            if waiting:
+                raise RuntimeError("request %d cannot be admitted even on an idle device" % waiting[0].rid)
+            continue
+        executor.step([r.handle for r in active])
+        steps += 1
+        max_active_seen = max(max_active_seen, len(active))
+        now = clock() - t0
+        still = []
+        for r in active:
+            if executor.levels_left(r.handle) == 0:
+                r.finished = now
+                executor.destroy(r.handle)
+                r.handle = None
+                done.append(r)
+            else:
+                still.append(r)
+        active = still
+        if log and steps % 10 == 0:
+            log("step %d: %d active, %d waiting, %d done" % (steps, len(active), len(waiting), len(done)))
+    wall = clock() - t0
+    lat = sorted(r.latency for r in done)
+    return {
+        "queries": len(done),
+        "wall_s": wall,
+        "queries_per_s": len(done) / wall if wall > 0 else None,
+        "p50_ms": 1e3 * percentile(lat, 50),
+        "p99_ms": 1e3 * percentile(lat, 99),
+        "mean_ms": 1e3 * sum(lat) / len(lat) if lat else None,
+        "steps": steps,
+        "max_active": max_active_seen,
+        "budget_rejections": rejected_attempts,
+        "requests": done,
+    }
+
+
+def percentile(xs, p):
+    if not xs:
+        return float("nan")
+    xs = sorted(xs)
+    k = (len(xs) - 1) * p / 100.0
+    f = int(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def poisson_arrivals(rate: float, count: int, rng) -> list[float]:
+    """Arrival offsets of a Poisson process of the given rate (per second)."""
+    t, out = 0.0, []
+    for _ in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        out.append(t)
+    return out
+

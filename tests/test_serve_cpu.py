@@ -1,0 +1,101 @@
+"""Scheduling logic of the continuous-batching server, on a stand-in executor
+with a simulated clock (no GPU): admission by budget, arrival order, overlap
+of requests that arrive while others run, and completion of every request."""
+import pytest
+
+from paper_2506_12761_amd.serve import BudgetExceeded, Executor, Request, serve
+
+LEVELS = {"intv": 19, "cov": 7, "idm": 23}
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+class FakeExecutor(Executor):
+    """Programs with a level count and a memory size; one step = step_s seconds."""
+
+    def __init__(self, clock, budget, step_s=0.1):
+        self.clock, self.budget, self.step_s = clock, budget, step_s
+        self.used = 0
+        self.left = {}
+        self.size = {}
+        self.step_log = []
+        self._n = 0
+
+    def create(self, req):
+        need = req.M
+        if self.used + need > self.budget:
+            raise BudgetExceeded("no room")
+        self._n += 1
+        h = self._n
+        self.used += need
+        self.left[h] = LEVELS[req.mode]
+        self.size[h] = need
+        return h
+
+    def step(self, handles):
+        self.step_log.append(sorted(handles))
+        for h in handles:
+            self.left[h] = max(0, self.left[h] - 1)
+        self.clock.t += self.step_s
+
+    def levels_left(self, h):
+        return self.left[h]
+
+    def destroy(self, h):
+        self.used -= self.size.pop(h)
+        del self.left[h]
+
+
+def _reqs(spec):
+    return [Request(i, client=i % 3, mode=m, M=M, l_I=16, l_S=64, d=2, arrival=t) for i, (m, M, t) in enumerate(spec)]
+
+
+def test_all_complete_and_overlap():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, budget=10_000)
+    reqs = _reqs([("intv", 100, 0.0), ("cov", 100, 0.35), ("idm", 100, 0.5)])
+    st = serve(reqs, ex, clock=clk, sleep=clk.sleep)
+    assert st["queries"] == 3
+    by = {r.rid: r for r in st["requests"]}
+    # request 1 (7 levels) arrives while request 0 runs and finishes first
+    assert by[1].admitted < by[0].finished and by[1].finished < by[0].finished
+    assert abs(by[0].latency - 19 * 0.1) < 1e-9
+    assert st["max_active"] == 3
+    # steps merge the active requests
+    assert any(len(s) == 3 for s in ex.step_log)
+
+
+def test_budget_admission_waits_for_memory():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, budget=250)
+    reqs = _reqs([("cov", 100, 0.0), ("cov", 100, 0.0), ("cov", 100, 0.0), ("idm", 200, 0.0)])
+    st = serve(reqs, ex, clock=clk, sleep=clk.sleep)
+    assert st["queries"] == 4 and st["budget_rejections"] > 0
+    by = {r.rid: r for r in st["requests"]}
+    assert by[2].admitted >= by[0].finished  # third waits for the first two
+    assert by[3].admitted >= by[2].finished  # arrival order, no overtaking
+    assert ex.used == 0
+
+
+def test_request_larger_than_device_is_an_error():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, budget=50)
+    with pytest.raises(RuntimeError):
+        serve(_reqs([("idm", 100, 0.0)]), ex, clock=clk, sleep=clk.sleep)
+
+
+def test_idle_gaps_advance_to_next_arrival():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, budget=1000)
+    st = serve(_reqs([("cov", 10, 0.0), ("cov", 10, 5.0)]), ex, clock=clk, sleep=clk.sleep)
+    lat = sorted(r.latency for r in st["requests"])
+    assert all(abs(x - 0.7) < 1e-9 for x in lat)
