@@ -165,6 +165,21 @@ def encrypt_bits(keys: Keys, bits_arr, masks, noise) -> np.ndarray:
     return out.reshape(shape + (n + 1,))
 
 
+def encrypt_bits_np(keys: Keys, bits_arr, masks, noise) -> np.ndarray:
+    """Same as encrypt_bits, vectorised with numpy (b = <a, s> + Ecd(bit) + e mod 2^32)."""
+    b = np.asarray(bits_arr).astype(np.uint64)
+    shape = b.shape
+    m = _u32(masks).reshape(-1, n)
+    dot = (m.astype(np.uint64) * keys.s.astype(np.uint64)[None, :]).sum(axis=1)
+    mu = np.where(b.reshape(-1) == 1, MU, 2**32 - MU).astype(np.uint64)
+    e = np.asarray(noise, np.int64).reshape(-1).astype(np.uint64)
+    body = (dot + mu + e) & np.uint64(0xFFFFFFFF)
+    out = np.empty((m.shape[0], n + 1), np.uint32)
+    out[:, :n] = m
+    out[:, n] = body.astype(np.uint32)
+    return out.reshape(shape + (n + 1,))
+
+
 def trivial(bit: int) -> np.ndarray:
     """Noiseless ciphertext (0, Ecd(bit))."""
     ct = np.zeros(n + 1, np.uint32)

@@ -81,8 +81,20 @@ def encrypt_workload(keys: O.Keys, P: dict, seed: int) -> dict:
             out[name] = np.zeros(b.shape + (O.n + 1,), np.uint32)
             continue
         masks, noise = synth.lwe_randomness(seed, "enc:" + name, b.size)
-        out[name] = O.encrypt_bits(keys, b, masks, noise)
+        out[name] = O.encrypt_bits_np(keys, b, masks, noise)
     return out
+
+
+def record_slice(P: dict, enc: dict, idx) -> tuple[dict, dict]:
+    """The sub-workload made of records `idx` (same query), for sampled checks."""
+    idx = np.asarray(idx)
+    Q = dict(P)
+    Q["M"] = len(idx)
+    Q["loc"] = P["loc"][idx]
+    Q["pay"] = P["pay"][idx]
+    Q["v"] = P["v"][idx]
+    e = {"query": enc["query"], "db_loc": enc["db_loc"][idx], "db_pay": enc["db_pay"][idx]}
+    return Q, e
 
 
 def graph_for(mode: str, M: int, l: int, lS: int, d: int, optimized: bool = True):

@@ -64,9 +64,11 @@ __device__ __forceinline__ void wave_transpose(Poly2& v, uint2* buf, int lane) {
   }
 }
 
-// Cooley-Tukey: (x, y) -> (x + w y, x - w y); in and out in [0, 4P).
+// Cooley-Tukey: (x, y) -> (x + w y, x - w y); in and out in [0, 4P).  With
+// CANON the input x is known to be < 2P already (first stage: canonical digits).
+template <bool CANON = false>
 __device__ __forceinline__ void bfly_ct(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp, uint32_t p) {
-  const uint32_t u = csub(x, 2 * p);
+  const uint32_t u = CANON ? x : csub(x, 2 * p);
   const uint32_t t = shoup(y, w, wp, p);
   x = u + t;
   y = u - t + 2 * p;
@@ -84,8 +86,8 @@ __device__ __forceinline__ void fwd_stage(Poly2& v, const Tw* tw, int lane) {
   for (int r = 0; r < 16; ++r) {
     if (r & (1 << RB)) continue;
     const Tw w = tw[(1 << S) + (LAY(lane, r) >> (10 - S))];
-    bfly_ct(v.a[r], v.a[r | (1 << RB)], w.x, w.y, P1);
-    bfly_ct(v.b[r], v.b[r | (1 << RB)], w.z, w.w, P2);
+    bfly_ct<S == 0>(v.a[r], v.a[r | (1 << RB)], w.x, w.y, P1);
+    bfly_ct<S == 0>(v.b[r], v.b[r | (1 << RB)], w.z, w.w, P2);
   }
 }
 template <int S, int (*LAY)(int, int), int RB>
@@ -99,7 +101,7 @@ __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
   }
 }
 
-// Forward: layout A (coefficient order, values < 4P) -> layout C (transform order, < 4P).
+// Forward: layout A (coefficient order, canonical values < P) -> layout C (transform order, < 4P).
 __device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, int lane) {
   fwd_stage<0, lay_a, 3>(v, tw, lane);
   fwd_stage<1, lay_a, 2>(v, tw, lane);

@@ -144,3 +144,11 @@ def test_schoolbook_bootstrap_equals_transform_bootstrap(oracle_keys):
     finally:
         O.lib().orc_set_schoolbook(0)
     assert np.array_equal(ref, sb)
+
+
+def test_vectorised_encryption_matches_scalar(oracle_keys):
+    masks, noise = synth.lwe_randomness(0x5EED0004, "vec", 40)
+    bitsv = np.random.default_rng(2).integers(0, 2, 40)
+    a = O.encrypt_bits(oracle_keys, bitsv, masks, noise)
+    b = O.encrypt_bits_np(oracle_keys, bitsv, masks, noise)
+    assert np.array_equal(a, b)
