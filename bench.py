@@ -41,6 +41,19 @@ OPS_PER_MODMUL = 16
 PEAK_MODMUL = VALU_LANE_OPS / OPS_PER_MODMUL  # 2.4576e12 modmul/s
 
 # A workload is one or more programs run together (their levels merged).
+# HBM-side traffic of br_kernel per launch on the default workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; copy-calibrated), valid only
+# for the kernel sources it was measured on (their sha256 prefix).
+TRAFFIC_MEASURED = {"kernel_sha": "fa9ed71a08e556b7", "bytes_per_launch": 5.16634e+08}
+KERNEL_SOURCES = ("kernels.hip", "wave_ntt.h", "rns.h", "vlp_api.cpp")
+
+
+def kernel_sha() -> str:
+    import hashlib
+    d = os.path.join(ROOT, "paper_2506_12761_amd", "csrc")
+    return hashlib.sha256(b"".join(open(os.path.join(d, n), "rb").read() for n in KERNEL_SOURCES)).hexdigest()[:16]
+
+
 WORKLOADS = {
     "intv-1024": dict(label="interval validation, 1024 records, 16-bit 2-D boxes",
                       programs=[dict(mode="intv", M=1024, l=16, lS=0, d=2)]),
@@ -104,6 +117,51 @@ def cpu_baseline(seconds: float, threads: int):
     return {"value": total / el, "unit": "bootstraps/s", "cores": threads, "kind": "oracle",
             "sample": "%d AND gates (1 blind rotation + 1 key switch each) on uniform ciphertexts, "
                       "%d threads, %.1f s wall" % (total, threads, el)}
+
+
+# Query shapes of the paper's four datasets (Table 3: records M, interval or
+# identifier bits l_I, payload bits l_S), with the modes Table 4 runs on them.
+TABLE3 = [("covid-kor", "intv", 9, 16, 9), ("covid-kor", "idm", 9, 16, 9), ("covid-usa", "intv", 58, 16, 22),
+          ("covid-usa", "idm", 58, 16, 22), ("gdacs", "cov", 9, 16, 16), ("weather-usa", "idm", 304, 16, 128)]
+
+
+def table3_bench(args):
+    """One full query (Algorithm 3) per Table-3 shape, baseline circuits
+    (Alg. 7 AND chain, Alg. 10 XOR chain) and optimized circuits (Alg. 11/12,
+    XOR tree); synthetic uniform data of those shapes; latency per query."""
+    from paper_2506_12761_amd import synth, vlp
+    ctx = vlp.Context(0)
+    bk, ksk = synth.uniform_keys(0x5EED0006)
+    ks = ctx.load_keys(bk, ksk)
+    rows = []
+    for k, (name, mode, M, l, lS) in enumerate(TABLE3):
+        d = 1 if mode == "idm" else 2
+        qs = (d, l) if mode != "idm" else (l,)
+        ls = {"intv": (M, d, 2, l), "cov": (M, d, l), "idm": (M, l)}[mode]
+        q = ctx.tensor(synth.uniform_ciphertexts(k, "q", qs))
+        loc = ctx.tensor(synth.uniform_ciphertexts(k, "l", ls))
+        pay = ctx.tensor(synth.uniform_ciphertexts(k, "p", (M, lS)))
+        R, v = ctx.empty(lS, 631), ctx.empty(M, 631)
+        rec = {"dataset": name, "mode": mode, "M": M, "l_I": l, "l_S": lS}
+        for opt in (False, True):
+            sh = vlp.make_shape(mode, M, l, lS, d, opt)
+            plan = vlp.vlp_plan_counts(sh)
+            vlp.vlp_evaluate(ctx.ctx, ks, sh, q, loc, pay, R, v)  # build + warm
+            ctx.sync()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                vlp.vlp_evaluate(ctx.ctx, ks, sh, q, loc, pay, R, v)
+            ctx.sync()
+            dt = (time.perf_counter() - t0) / args.steps
+            rec["opt" if opt else "base"] = {"s": dt, "blind_rotations": plan["blind_rotations"],
+                                              "levels": plan["levels"]}
+        rec["speedup_opt_vs_base"] = rec["base"]["s"] / rec["opt"]["s"]
+        log(json.dumps(rec))
+        rows.append(rec)
+    print(json.dumps({"metric": "PIR query latency per Table-3 shape, baseline vs optimized circuits, 1 GPU",
+                      "unit": "s", "higher_is_better": False, "data": "synthetic (uniform words of the dataset shapes)",
+                      "steps": args.steps, "rows": rows}), flush=True)
+    ctx.close()
 
 
 def serve_bench(args):
@@ -186,11 +244,14 @@ def main():
     ap.add_argument("--records", type=int, default=0, help="override the record count of every program")
     ap.add_argument("--tuned", action="store_true", help="apply the cached autotuner result")
     ap.add_argument("--serve", action="store_true", help="run the serving experiment instead")
+    ap.add_argument("--table3", action="store_true", help="replay the paper's dataset shapes instead")
     ap.add_argument("--requests", type=int, default=12)
     ap.add_argument("--clients", type=int, default=3)
     ap.add_argument("--min-records", type=int, default=256)
     ap.add_argument("--max-records", type=int, default=2048)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device with a plain copy kernel (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -199,6 +260,18 @@ def main():
         sys.exit(2)
     if args.serve:
         return serve_bench(args)
+    if args.table3:
+        return table3_bench(args)
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.arange(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
 
     import numpy as np
     import torch
@@ -291,10 +364,17 @@ def main():
     if prof and prof["br"]["launches"]:
         br = prof["br"]
         avg_ms = br["ms"] / br["launches"]
+        # Algorithmic bytes per launch: the transformed key once (61,931,520 B), the two
+        # input ciphertexts (2 x 2,524 B) and the extracted output (4,100 B) per rotation.
+        alg_bytes = 61931520 + (2 * 2524 + 4100) * br["items"] / br["launches"]
         per_launch = MODMUL_PER_BR * br["items"] / br["launches"]
         achieved = per_launch / (avg_ms * 1e-3)
+        traffic = None
+        if args.workload == "intv-1024" and TRAFFIC_MEASURED["kernel_sha"] == kernel_sha():
+            traffic = TRAFFIC_MEASURED["bytes_per_launch"]
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MODMUL / 1e12,
-                    "unit": "Tmodmul/s", "frac": achieved / PEAK_MODMUL, "traffic": None,
+                    "unit": "Tmodmul/s", "frac": achieved / PEAK_MODMUL, "traffic": traffic,
+                    "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": alg_bytes,
                     "kernel": "br_kernel", "launches": br["launches"], "avg_launch_ms": avg_ms,
                     "ks_kernel_ms_share": prof["ks"]["ms"] / max(1e-9, prof["ks"]["ms"] + br["ms"])}
 

@@ -146,13 +146,23 @@ size_t br_blocks(const vlp_ctx* ctx) { return (size_t)ctx->num_cus * ctx->tune.b
 int mark_begin(vlp_ctx* ctx);
 void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
 
+// Blind rotations are launched in chunks of one item per resident wavefront
+// (CUs x workgroups per CU x waves per workgroup).  Wavefronts that start
+// together walk the key in step, so each key row reaches L2 once for many of
+// them; a persistent loop over many rounds lets them drift apart and
+// re-fetch the key (measured: ~0.5 MB vs up to ~36 MB of key traffic per
+// blind rotation).
 int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
-  if (count == 0) return 0;
-  const int m = mark_begin(ctx);
-  const int e = launch_br(items, count, ctx->tw_fwd, ctx->tune.br_waves_per_block, (uint32_t)br_blocks(ctx),
-                          ctx->stream);
-  mark_end(ctx, m, 0, count);
-  return e;
+  const uint32_t waves = ctx->tune.br_waves_per_block, blocks = (uint32_t)br_blocks(ctx);
+  const uint32_t chunk = blocks * waves;
+  for (uint32_t first = 0; first < count; first += chunk) {
+    const uint32_t n = std::min(chunk, count - first);
+    const int m = mark_begin(ctx);
+    const int e = launch_br(items + first, n, ctx->tw_fwd, waves, blocks, ctx->stream);
+    mark_end(ctx, m, 0, n);
+    if (e != 0) return e;
+  }
+  return 0;
 }
 
 int timed_ks(vlp_ctx* ctx, const KsItem* items, uint32_t count, const uint32_t* ksk) {
