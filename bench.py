@@ -164,6 +164,55 @@ def table3_bench(args):
     ctx.close()
 
 
+def server_enc_bench(args):
+    """ServerEnc (Alg. 2) of the identifier-match database of 65,536 records
+    (32-bit identifiers, 64 payload bits: 6,291,456 ciphertexts, 15.9 GB of
+    public key) from a device-resident public key, out of place (the HBM
+    roofline case: every word read once and written once) and in place (only
+    the body words change).  Public key and data are seeded synthetic words."""
+    import torch
+
+    from paper_2506_12761_amd import vlp
+    M, l, lS = 65536, 32, 64
+    ctx = vlp.Context(0)
+    dev = ctx.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(0x5EED0007)
+    with torch.cuda.stream(ctx.stream):
+        pk_loc = torch.empty((M, l, 631), dtype=torch.int32, device=dev).random_(generator=g)
+        pk_pay = torch.empty((M, lS, 631), dtype=torch.int32, device=dev).random_(generator=g)
+        loc = torch.randint(0, 2**31 - 1, (M,), dtype=torch.int64, device=dev, generator=g)
+        pay = torch.randint(0, 2, (M, lS), dtype=torch.uint8, device=dev, generator=g)
+        out_loc, out_pay = torch.empty_like(pk_loc), torch.empty_like(pk_pay)
+    ctx.sync()
+    sh = vlp.make_shape("idm", M, l, lS, 1)
+    count = M * (l + lS)
+    res = {}
+    for form, (o_loc, o_pay) in (("copy", (out_loc, out_pay)), ("inplace", (pk_loc, pk_pay))):
+        for _ in range(max(1, args.warmup)):
+            vlp.vlp_server_encrypt(ctx.ctx, sh, pk_loc, pk_pay, loc, pay, o_loc, o_pay)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(args.steps):
+            vlp.vlp_server_encrypt(ctx.ctx, sh, pk_loc, pk_pay, loc, pay, o_loc, o_pay)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[form] = {"ms_per_call": ms, "ciphertexts_per_s": count / (ms * 1e-3)}
+    alg = count * 631 * 4 * 2 + M * 8 + M * lS  # words read + written, values, payload bytes
+    gbs = alg / (res["copy"]["ms_per_call"] * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "ServerEnc (Alg. 2) ciphertexts/s at 1 GPU, device-resident public key",
+        "value": res["copy"]["ciphertexts_per_s"], "unit": "ciphertexts/s", "higher_is_better": True,
+        "steps": args.steps, "warmup": args.warmup, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "identifier-match database, 65536 records, 32-bit ids, 64 payload bits",
+                   "ciphertexts": count, "public_key_bytes": count * 631 * 4},
+        "forms": res,
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                     "traffic": None, "algorithmic_bytes_per_call": alg}}), flush=True)
+    ctx.close()
+
+
 def serve_bench(args):
     """Poisson stream of PIR queries, modes uniform over {IntV 16-bit, CoV 20-bit,
     IdM 32-bit}, records log-uniform in [min, max], 64 payload bits, one of
@@ -243,8 +292,12 @@ def main():
                     "(disables per-launch timing)")
     ap.add_argument("--records", type=int, default=0, help="override the record count of every program")
     ap.add_argument("--tuned", action="store_true", help="apply the cached autotuner result")
+    ap.add_argument("--br-waves", type=int, default=0, help="waves per blind-rotation workgroup (1, 2, 4, 8)")
+    ap.add_argument("--br-blocks", type=int, default=0, help="blind-rotation workgroups per CU the grid is sized for")
     ap.add_argument("--serve", action="store_true", help="run the serving experiment instead")
     ap.add_argument("--table3", action="store_true", help="replay the paper's dataset shapes instead")
+    ap.add_argument("--server-enc", action="store_true", help="time ServerEnc of a 65,536-record database instead")
+    ap.add_argument("--progress", action="store_true", help="wait for and report every circuit level")
     ap.add_argument("--requests", type=int, default=12)
     ap.add_argument("--clients", type=int, default=3)
     ap.add_argument("--min-records", type=int, default=256)
@@ -262,6 +315,8 @@ def main():
         return serve_bench(args)
     if args.table3:
         return table3_bench(args)
+    if args.server_enc:
+        return server_enc_bench(args)
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
@@ -291,6 +346,13 @@ def main():
     if args.tuned:
         from paper_2506_12761_amd import autotune
         log("cached tuning applied: %s" % autotune.load_cached(ctx, args.workload))
+    if args.br_waves or args.br_blocks:
+        t = vlp.vlp_get_tuning(ctx.ctx)
+        vlp.vlp_set_tuning(ctx.ctx, args.br_waves or t.br_waves_per_block, args.br_blocks or t.br_blocks_per_cu,
+                           t.ks_gates_per_block)
+    t = vlp.vlp_get_tuning(ctx.ctx)
+    launch = {"br_waves_per_block": t.br_waves_per_block, "br_blocks_per_cu": t.br_blocks_per_cu,
+              "ks_gates_per_block": t.ks_gates_per_block}
     progs, keep = [], []
     for k, p in enumerate(specs):
         mode, M, l, lS, d = p["mode"], p["M"], p["l"], p["lS"], p["d"]
@@ -314,7 +376,16 @@ def main():
     def step():
         for pr in progs:
             vlp.vlp_program_reset(ctx.ctx, pr)
-        if len(progs) == 1:
+        if args.progress:  # level by level, waiting for each (long workloads report as they go)
+            lvl = 0
+            while True:
+                rem = vlp.vlp_step(ctx.ctx, progs)
+                ctx.sync()
+                lvl += 1
+                log("level %d done" % lvl)
+                if not rem:
+                    break
+        elif len(progs) == 1:
             vlp.vlp_program_run(ctx.ctx, progs[0], use_graph=args.graph)
         else:
             while vlp.vlp_step(ctx.ctx, progs):
@@ -399,7 +470,7 @@ def main():
         "data": "synthetic (seeded uniform keys and ciphertexts)",
         "config": {"workload": wl["label"], "programs": specs,
                    "blind_rotations_per_step": br_step, "key_switches_per_step": ks_step,
-                   "levels": levels, "graph": bool(args.graph)},
+                   "levels": levels, "graph": bool(args.graph), "launch": launch},
         "gates_per_s": gates_step * args.steps / elapsed,
         "key_switches_per_s": ks_step * args.steps / elapsed,
         "plain_bootstraps_per_s": plain_rate,

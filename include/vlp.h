@@ -163,6 +163,24 @@ vlp_status vlp_gate(vlp_ctx *ctx, const vlp_keyset *ks, vlp_gate_op op, const ui
 vlp_status vlp_evaluate(vlp_ctx *ctx, const vlp_keyset *ks, const vlp_shape *shape, const uint32_t *query_dev,
                         const uint32_t *db_loc_dev, const uint32_t *db_pay_dev, uint32_t *R_dev, uint32_t *v_out_dev);
 
+/* ServerEnc (Alg. 2): the server encrypts its plaintext database under the
+ * client's public key (Alg. 1: one encryption of zero per database bit), so
+ * no secret key is needed: each slot becomes pk + (0, Ecd(bit)).
+ *   pk_loc / out_loc: location slots in db_loc_dev's layout of vlp_evaluate
+ *                     (IntV [M][d][2][l_I][631], CoV [M][d][l_I][631],
+ *                     IdM [M][l_I][631])
+ *   loc             : int64 values, IntV [M][d][2] (left, right bound),
+ *                     CoV [M][d], IdM [M]; slot bit j is bit j (LSB first) of
+ *                     the value's two's-complement form
+ *   pk_pay / out_pay: [M][l_S][631]; pay: [M][l_S] bytes, nonzero = bit 1
+ *                     (all three NULL when l_S = 0)
+ * All device pointers.  An output may equal its public key exactly (in
+ * place: only body words are written); otherwise outputs may not overlap any
+ * argument (VLP_EINVAL).  Enqueued on the context's stream; inputs must stay
+ * valid until it has run. */
+vlp_status vlp_server_encrypt(vlp_ctx *ctx, const vlp_shape *shape, const uint32_t *pk_loc, const uint32_t *pk_pay,
+                              const int64_t *loc, const uint8_t *pay, uint32_t *out_loc, uint32_t *out_pay);
+
 /* ---- Programs: an evaluation bound to its buffers, advanced level by level.
  * vlp_program_create builds the gate schedule of vlp_evaluate's arguments
  * and reserves its intermediate storage (VLP_EBUDGET if the budget cannot
@@ -189,7 +207,8 @@ vlp_status vlp_program_counts(const vlp_program *prog, uint64_t *gates, uint64_t
 vlp_status vlp_program_destroy(vlp_program *prog);
 
 /* ---- Tuning knobs of the batched kernels (picked by the autotuner).
- * br_waves_per_block: waves per workgroup of the blind-rotation kernel (1, 2, 4)
+ * br_waves_per_block: waves per workgroup of the blind-rotation kernel (1, 2, 4, 8;
+ *                     8 = two per SIMD at half the registers each)
  * br_blocks_per_cu  : resident workgroups per compute unit the grid is sized for
  * ks_gates_per_block: gates sharing one pass over the key-switching key */
 typedef struct {

@@ -19,7 +19,7 @@ from . import vlp
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
-SHAPES = [(w, b, k) for w in (1, 2, 4) for b in (1, 2, 4) for k in (4, 8, 16)
+SHAPES = [(w, b, k) for w in (1, 2, 4, 8) for b in (1, 2, 4) for k in (4, 8, 16)
           if w * b <= 8]
 
 

@@ -53,6 +53,9 @@ int launch_bk_transform(const uint32_t* bk_coeff, uint2* bk_ntt, const uint4* tw
 int launch_ksk_relayout(const uint32_t* ksk_in, uint32_t* ksk_out, void* stream);
 int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t waves_per_block, uint32_t blocks,
               void* stream);
+// ServerEnc over a flat [count][631] array; out == pk runs in place.
+int launch_server_enc(const uint32_t* pk, uint32_t* out, size_t count, const int64_t* vals, const uint8_t* bytes,
+                      uint32_t l, void* stream);
 int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream);
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
                          uint32_t cst, uint32_t mu, uint32_t* out, const uint2* bk, void* stream);

@@ -2,6 +2,8 @@
 // sample extraction, batched key switching, and small helpers.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "rns.h"
 #include "wave_ntt.h"
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t
       v.a[r] = x % P1;
       v.b[r] = x % P2;
     }
-    ntt_fwd(v, s_buf[wave], s_tw, lane);
+    ntt_fwd(v, s_buf[wave], s_tw, tw_fwd, lane);
     uint2* dst = bk_ntt + (size_t)poly * RING_N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -66,9 +68,15 @@ constexpr uint32_t DEC_OFFSET = (1u << 31) + (1u << 24) + (1u << 17) + (1u << 10
 typedef const uint64_t __attribute__((address_space(1))) g_u64;
 typedef const uint32_t __attribute__((address_space(1))) g_u32;
 
+// Up to 4 wavefronts per workgroup (one per SIMD) a wavefront may hold 512
+// registers: the key rows are prefetched and the accumulators are 64-bit.
+// With 8 (two per SIMD, so one hides the other's latencies) it has 256: the
+// key is read where it is used and the accumulators are 32-bit.
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict__ items, uint32_t count,
                                                          const Tw* __restrict__ tw_fwd) {
+  constexpr bool kPrefetchKey = WAVES <= 4, kWideAcc = WAVES <= 4;
+  using Acc = typename std::conditional<kWideAcc, uint64_t, uint32_t>::type;
   __shared__ Tw s_tw[RING_N];                   // twiddles of both primes (16 KB)
   __shared__ uint2 s_buf[WAVES][RING_N];        // per-wave transpose scratch
   __shared__ uint32_t s_acc[WAVES][2][RING_N];  // per-wave accumulator (A, B), coefficient order
@@ -109,9 +117,12 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
       const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
       if (ab == 0) continue;
       // External product BK_i x (X^ab acc - acc): the six digit polynomials are
-      // transformed one at a time; each product with the key (Montgomery form)
-      // is reduced to [0, P) and summed lazily (six terms stay below 6P < 2^32).
-      uint32_t m0a[16], m0b[16], m1a[16], m1b[16];
+      // transformed one at a time and multiplied into the accumulators.
+      //  - wide (64-bit) accumulators take canonical residues: six products stay
+      //    below P * 2^32, the input range of one Montgomery reduction at the end;
+      //  - narrow (32-bit) accumulators reduce each product to [0, P) and sum
+      //    lazily (six terms < 6P < 2^32).
+      Acc m0a[16], m0b[16], m1a[16], m1b[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) m0a[r] = m0b[r] = m1a[r] = m1b[r] = 0;
       wave_lds_sync();  // accumulator updates of the previous step are visible
@@ -128,13 +139,17 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
         }
 #pragma unroll 1
         for (int lev = 0; lev < ELL; ++lev) {
-          // This row's key words are requested first; the transform hides their latency.
+          // {residue mod P1 (low word), residue mod P2 (high word)} of the two key
+          // rows of this digit; with registers to spare they are requested before
+          // the transform, which hides their latency.
           const g_u64* k0 = (const g_u64*)(bk_i + (size_t)((c * ELL + lev) * 2) * RING_N);
-          uint64_t b0[16], b1[16];  // {residue mod P1 (low word), residue mod P2 (high word)}
+          uint64_t b0[16], b1[16];
+          if constexpr (kPrefetchKey) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            b0[r] = k0[r * 64 + lane];
-            b1[r] = k0[RING_N + r * 64 + lane];
+            for (int r = 0; r < 16; ++r) {
+              b0[r] = k0[r * 64 + lane];
+              b1[r] = k0[RING_N + r * 64 + lane];
+            }
           }
           const int shift = 32 - BG_BIT * (lev + 1);
           Poly2 v;
@@ -144,14 +159,26 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
             v.a[r] = res_of(d, P1);
             v.b[r] = res_of(d, P2);
           }
-          ntt_fwd(v, buf, s_tw, lane);
+          ntt_fwd(v, buf, s_tw, tw_fwd, lane);
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const uint32_t da = csub(v.a[r], 2 * P1), db = csub(v.b[r], 2 * P2);  // [0, 2P)
-            m0a[r] += redc((uint64_t)da * (uint32_t)b0[r], P1, P1_INV);
-            m0b[r] += redc((uint64_t)db * (uint32_t)(b0[r] >> 32), P2, P2_INV);
-            m1a[r] += redc((uint64_t)da * (uint32_t)b1[r], P1, P1_INV);
-            m1b[r] += redc((uint64_t)db * (uint32_t)(b1[r] >> 32), P2, P2_INV);
+            if constexpr (!kPrefetchKey) {
+              b0[r] = k0[r * 64 + lane];
+              b1[r] = k0[RING_N + r * 64 + lane];
+            }
+            if constexpr (kWideAcc) {
+              const uint32_t da = csub(csub(v.a[r], 2 * P1), P1), db = csub(csub(v.b[r], 2 * P2), P2);  // [0, P)
+              m0a[r] += (uint64_t)da * (uint32_t)b0[r];
+              m0b[r] += (uint64_t)db * (uint32_t)(b0[r] >> 32);
+              m1a[r] += (uint64_t)da * (uint32_t)b1[r];
+              m1b[r] += (uint64_t)db * (uint32_t)(b1[r] >> 32);
+            } else {
+              const uint32_t da = csub(v.a[r], 2 * P1), db = csub(v.b[r], 2 * P2);  // [0, 2P)
+              m0a[r] += redc((uint64_t)da * (uint32_t)b0[r], P1, P1_INV);
+              m0b[r] += redc((uint64_t)db * (uint32_t)(b0[r] >> 32), P2, P2_INV);
+              m1a[r] += redc((uint64_t)da * (uint32_t)b1[r], P1, P1_INV);
+              m1b[r] += redc((uint64_t)db * (uint32_t)(b1[r] >> 32), P2, P2_INV);
+            }
           }
         }
       }
@@ -159,11 +186,16 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
       for (int c = 0; c < 2; ++c) {
         Poly2 v;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {  // [0, 6P) -> [0, 2P)
-          v.a[r] = csub(csub(c ? m1a[r] : m0a[r], 4 * P1), 2 * P1);
-          v.b[r] = csub(csub(c ? m1b[r] : m0b[r], 4 * P2), 2 * P2);
+        for (int r = 0; r < 16; ++r) {
+          if constexpr (kWideAcc) {
+            v.a[r] = redc(c ? m1a[r] : m0a[r], P1, P1_INV);
+            v.b[r] = redc(c ? m1b[r] : m0b[r], P2, P2_INV);
+          } else {  // [0, 6P) -> [0, 2P)
+            v.a[r] = csub(csub(c ? m1a[r] : m0a[r], 4 * P1), 2 * P1);
+            v.b[r] = csub(csub(c ? m1b[r] : m0b[r], 4 * P2), 2 * P2);
+          }
         }
-        ntt_inv(v, buf, s_tw, lane);
+        ntt_inv(v, buf, s_tw, tw_fwd, lane);
         uint32_t* poly = acc + c * RING_N;
 #pragma unroll
         for (int r = 0; r < 16; ++r) poly[r * 64 + lane] += crt_lift_u32(csub(v.a[r], P1), csub(v.b[r], P2));
@@ -285,6 +317,68 @@ __global__ void negate_kernel(const uint32_t* a, uint32_t* out, size_t words) {
     out[i] = 0u - a[i];
 }
 
+// ServerEnc (Alg. 2): ciphertext t of a flat [count][631] array becomes
+// pk[t] + (0, Ecd(bit_t)).  bit_t is bit (t mod l) of the int64 value t / l
+// (LSB first, two's complement) when `vals` is given, else bytes[t] != 0.
+__device__ __forceinline__ uint32_t enc_word(const int64_t* vals, const uint8_t* bytes, uint32_t l, size_t t) {
+  const uint32_t bit = vals ? (uint32_t)(((uint64_t)vals[t / l] >> (t % l)) & 1u) : (uint32_t)(bytes[t] != 0);
+  return bit ? MU : 0u - MU;
+}
+
+// Out of place: four consecutive words per thread (16-byte accesses; pk and
+// out 16-byte aligned), the last words % 4 words by the first threads.
+__global__ void server_enc_copy_kernel(const uint4* __restrict__ pk, uint4* __restrict__ out, size_t count,
+                                       const int64_t* __restrict__ vals, const uint8_t* __restrict__ bytes,
+                                       uint32_t l) {
+  const size_t words = count * CT_n, quads = words / 4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
+    uint4 w = pk[q];
+    const size_t w0 = 4 * q;
+    const size_t t = w0 / CT_n;
+    const uint32_t r = (uint32_t)(w0 - t * CT_n);  // word index of w.x inside ciphertext t
+    // The body word (CT_n - 1) is one of the four iff r >= CT_n - 4.
+    if (r >= CT_n - 4) {
+      const uint32_t e = enc_word(vals, bytes, l, t);
+      switch (CT_n - 1 - r) {
+        case 0: w.x += e; break;
+        case 1: w.y += e; break;
+        case 2: w.z += e; break;
+        default: w.w += e; break;
+      }
+    }
+    out[q] = w;
+  }
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid < words - 4 * quads) {
+    const size_t wi = 4 * quads + tid;
+    const size_t t = wi / CT_n;
+    uint32_t v = reinterpret_cast<const uint32_t*>(pk)[wi];
+    if (wi - t * CT_n == CT_n - 1) v += enc_word(vals, bytes, l, t);
+    reinterpret_cast<uint32_t*>(out)[wi] = v;
+  }
+}
+
+// Word-granular form of the copy for buffers that are not 16-byte aligned.
+__global__ void server_enc_word_kernel(const uint32_t* __restrict__ pk, uint32_t* __restrict__ out, size_t count,
+                                       const int64_t* __restrict__ vals, const uint8_t* __restrict__ bytes,
+                                       uint32_t l) {
+  const size_t words = count * CT_n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t t = i / CT_n;
+    uint32_t v = pk[i];
+    if (i - t * CT_n == CT_n - 1) v += enc_word(vals, bytes, l, t);
+    out[i] = v;
+  }
+}
+
+// In place (out == pk): only the body words change.
+__global__ void server_enc_inplace_kernel(uint32_t* ct, size_t count, const int64_t* __restrict__ vals,
+                                          const uint8_t* __restrict__ bytes, uint32_t l) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
+    ct[t * CT_n + CT_n - 1] += enc_word(vals, bytes, l, t);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -314,6 +408,7 @@ int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t
     case 1: hipLaunchKernelGGL(br_kernel<1>, dim3(blocks), dim3(64), 0, S(stream), items, count, tw_fwd); break;
     case 2: hipLaunchKernelGGL(br_kernel<2>, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd); break;
     case 4: hipLaunchKernelGGL(br_kernel<4>, dim3(blocks), dim3(256), 0, S(stream), items, count, tw_fwd); break;
+    case 8: hipLaunchKernelGGL(br_kernel<8>, dim3(blocks), dim3(512), 0, S(stream), items, count, tw_fwd); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
@@ -355,6 +450,29 @@ int launch_make_ks_items(KsItem* items, uint32_t count, const uint32_t* u1, cons
 int launch_negate(const uint32_t* a, uint32_t* out, size_t words, void* stream) {
   if (words == 0) return 0;
   hipLaunchKernelGGL(negate_kernel, dim3(1024), dim3(256), 0, S(stream), a, out, words);
+  return (int)hipGetLastError();
+}
+
+int launch_server_enc(const uint32_t* pk, uint32_t* out, size_t count, const int64_t* vals, const uint8_t* bytes,
+                      uint32_t l, void* stream) {
+  if (count == 0) return 0;
+  const size_t words = count * CT_n;
+  if (pk == out) {
+    const size_t blocks = std::min<size_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(server_enc_inplace_kernel, dim3((uint32_t)blocks), dim3(256), 0, S(stream), out, count, vals,
+                       bytes, l);
+  } else if ((((uintptr_t)pk | (uintptr_t)out) & 15) == 0) {
+    // Enough threads for the word tail (< 4) in the first block; 16 waves per CU
+    // in flight, grid-stride beyond that.
+    const size_t quads = words / 4;
+    const size_t blocks = std::max<size_t>(1, std::min<size_t>((quads + 255) / 256, 4096));
+    hipLaunchKernelGGL(server_enc_copy_kernel, dim3((uint32_t)blocks), dim3(256), 0, S(stream),
+                       reinterpret_cast<const uint4*>(pk), reinterpret_cast<uint4*>(out), count, vals, bytes, l);
+  } else {
+    const size_t blocks = std::min<size_t>((words + 255) / 256, 8192);
+    hipLaunchKernelGGL(server_enc_word_kernel, dim3((uint32_t)blocks), dim3(256), 0, S(stream), pk, out, count, vals,
+                       bytes, l);
+  }
   return (int)hipGetLastError();
 }
 

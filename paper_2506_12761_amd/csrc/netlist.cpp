@@ -99,16 +99,22 @@ std::vector<Operand> bits(Operand (*mk)(uint32_t), uint32_t base, uint32_t l) {
 
 }  // namespace
 
-bool build_netlist(const vlp_shape& sh, Netlist& nl, const char** why) {
-  nl = Netlist();
-  const uint32_t M = sh.M, l = sh.l_I, lS = sh.l_S;
-  const uint32_t d = sh.mode == VLP_IDM ? 1 : sh.d;
+bool shape_valid(const vlp_shape& sh, const char** why) {
+  const uint32_t M = sh.M, l = sh.l_I, lS = sh.l_S, d = sh.d;
   if (sh.mode != VLP_INTV && sh.mode != VLP_COV && sh.mode != VLP_IDM) { *why = "unknown mode"; return false; }
   if (M == 0 || M > (1u << 24)) { *why = "M must be in [1, 2^24]"; return false; }
   if (l < 1 || l > 64) { *why = "l_I must be in [1, 64]"; return false; }
   if (sh.mode == VLP_INTV && l < 2) { *why = "IntV needs l_I >= 2"; return false; }
   if (lS > 1024) { *why = "l_S must be <= 1024"; return false; }
   if (sh.mode != VLP_IDM && (d < 1 || d > 2)) { *why = "d must be 1 or 2"; return false; }
+  return true;
+}
+
+bool build_netlist(const vlp_shape& sh, Netlist& nl, const char** why) {
+  nl = Netlist();
+  const uint32_t M = sh.M, l = sh.l_I, lS = sh.l_S;
+  const uint32_t d = sh.mode == VLP_IDM ? 1 : sh.d;
+  if (!shape_valid(sh, why)) return false;
   nl.M = M;
   nl.l_S = lS;
   Builder B{nl};

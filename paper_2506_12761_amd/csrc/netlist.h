@@ -42,6 +42,8 @@ struct Netlist {
 
 // Builds the gate netlist of Algorithm 3 for `shape` (validation by IntV,
 // CoV or IdM, zero-out, aggregation).  Returns false for shapes out of range.
+// Limits every call taking a shape enforces (mode, M, l_I, l_S, d).
+bool shape_valid(const vlp_shape& shape, const char** why);
 bool build_netlist(const vlp_shape& shape, Netlist& out, const char** why);
 
 }  // namespace vlp

@@ -343,7 +343,7 @@ extern "C" vlp_status vlp_get_tuning(const vlp_ctx* ctx, vlp_tuning* t) {
 extern "C" vlp_status vlp_set_tuning(vlp_ctx* ctx, const vlp_tuning* t) {
   if (!ctx || !t) return VLP_EINVAL;
   const uint32_t w = t->br_waves_per_block, g = t->ks_gates_per_block;
-  if (!(w == 1 || w == 2 || w == 4)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2 or 4");
+  if (!(w == 1 || w == 2 || w == 4 || w == 8)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2, 4 or 8");
   if (t->br_blocks_per_cu < 1 || t->br_blocks_per_cu > 64) return fail(ctx, VLP_EINVAL, "br_blocks_per_cu out of [1, 64]");
   if (!(g == 4 || g == 8 || g == 16)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 4, 8 or 16");
   ctx->tune = *t;
@@ -494,6 +494,35 @@ static vlp_status shape_words(const vlp_shape* sh, size_t* q, size_t* loc, size_
   *q = d * l;
   *loc = sh->mode == VLP_INTV ? M * d * 2 * l : M * d * l;
   *pay = M * sh->l_S;
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_server_encrypt(vlp_ctx* ctx, const vlp_shape* shape, const uint32_t* pk_loc,
+                                         const uint32_t* pk_pay, const int64_t* loc, const uint8_t* pay,
+                                         uint32_t* out_loc, uint32_t* out_pay) {
+  if (!ctx) return VLP_EINVAL;
+  if (!shape) return fail(ctx, VLP_EINVAL, "shape is NULL");
+  const char* why = "";
+  if (!shape_valid(*shape, &why)) return fail(ctx, VLP_EINVAL, "bad shape: %s", why);
+  size_t wq, n_loc, n_pay;
+  shape_words(shape, &wq, &n_loc, &n_pay);
+  if (!pk_loc || !loc || !out_loc) return fail(ctx, VLP_EINVAL, "pk_loc, loc and out_loc are required");
+  if (n_pay && (!pk_pay || !pay || !out_pay)) return fail(ctx, VLP_EINVAL, "l_S > 0 needs pk_pay, pay and out_pay");
+  const size_t b_loc = n_loc * CT_n * 4, b_pay = n_pay * CT_n * 4;
+  const size_t b_vals = n_loc / shape->l_I * sizeof(int64_t), b_bits = n_pay;
+  // Each output either is its own public key (in place) or overlaps nothing.
+  if (out_loc != pk_loc && ranges_overlap(out_loc, b_loc, pk_loc, b_loc))
+    return fail(ctx, VLP_EINVAL, "out_loc partly overlaps pk_loc");
+  if (n_pay && out_pay != pk_pay && ranges_overlap(out_pay, b_pay, pk_pay, b_pay))
+    return fail(ctx, VLP_EINVAL, "out_pay partly overlaps pk_pay");
+  if (ranges_overlap(out_loc, b_loc, loc, b_vals) || (n_pay && ranges_overlap(out_loc, b_loc, pk_pay, b_pay)) ||
+      (n_pay && ranges_overlap(out_loc, b_loc, pay, b_bits)))
+    return fail(ctx, VLP_EINVAL, "out_loc overlaps another argument");
+  if (n_pay && (ranges_overlap(out_pay, b_pay, pk_loc, b_loc) || ranges_overlap(out_pay, b_pay, out_loc, b_loc) ||
+                ranges_overlap(out_pay, b_pay, loc, b_vals) || ranges_overlap(out_pay, b_pay, pay, b_bits)))
+    return fail(ctx, VLP_EINVAL, "out_pay overlaps another argument");
+  LAUNCHCHECK(ctx, launch_server_enc(pk_loc, out_loc, n_loc, loc, nullptr, shape->l_I, ctx->stream));
+  if (n_pay) LAUNCHCHECK(ctx, launch_server_enc(pk_pay, out_pay, n_pay, nullptr, pay, 1, ctx->stream));
   return VLP_OK;
 }
 

@@ -102,11 +102,14 @@ __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
 }
 
 // Forward: layout A (coefficient order, canonical values < P) -> layout C (transform order, < 4P).
-__device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, int lane) {
-  fwd_stage<0, lay_a, 3>(v, tw, lane);
-  fwd_stage<1, lay_a, 2>(v, tw, lane);
-  fwd_stage<2, lay_a, 1>(v, tw, lane);
-  fwd_stage<3, lay_a, 0>(v, tw, lane);
+// Stages 0..3 use wavefront-uniform twiddles (their index depends only on the
+// register), read through `gtw` (the table in global memory: scalar loads into
+// SGPRs); the other stages read the LDS copy `tw` per lane.
+__device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, const Tw* __restrict__ gtw, int lane) {
+  fwd_stage<0, lay_a, 3>(v, gtw, lane);
+  fwd_stage<1, lay_a, 2>(v, gtw, lane);
+  fwd_stage<2, lay_a, 1>(v, gtw, lane);
+  fwd_stage<3, lay_a, 0>(v, gtw, lane);
   wave_transpose<lay_a, lay_b>(v, buf, lane);
   fwd_stage<4, lay_b, 3>(v, tw, lane);
   fwd_stage<5, lay_b, 2>(v, tw, lane);
@@ -118,7 +121,7 @@ __device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, int 
 }
 
 // Inverse without 1/N: layout C (values < 2P) -> layout A (values < 2P).
-__device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, int lane) {
+__device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, const Tw* __restrict__ gtw, int lane) {
   inv_stage<9, lay_c, 0>(v, tw, lane);
   inv_stage<8, lay_c, 1>(v, tw, lane);
   wave_transpose<lay_c, lay_b>(v, buf, lane);
@@ -127,10 +130,10 @@ __device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, int 
   inv_stage<5, lay_b, 2>(v, tw, lane);
   inv_stage<4, lay_b, 3>(v, tw, lane);
   wave_transpose<lay_b, lay_a>(v, buf, lane);
-  inv_stage<3, lay_a, 0>(v, tw, lane);
-  inv_stage<2, lay_a, 1>(v, tw, lane);
-  inv_stage<1, lay_a, 2>(v, tw, lane);
-  inv_stage<0, lay_a, 3>(v, tw, lane);
+  inv_stage<3, lay_a, 0>(v, gtw, lane);
+  inv_stage<2, lay_a, 1>(v, gtw, lane);
+  inv_stage<1, lay_a, 2>(v, gtw, lane);
+  inv_stage<0, lay_a, 3>(v, gtw, lane);
 }
 
 }  // namespace vlp

@@ -29,7 +29,7 @@ MU = 1 << 29
 # Every entry point of include/vlp.h.
 EXPORTS = [
     "vlp_version", "vlp_default_params", "vlp_ctx_create", "vlp_ctx_destroy", "vlp_last_error", "vlp_mem_info",
-    "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_evaluate",
+    "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_evaluate", "vlp_server_encrypt",
     "vlp_program_create", "vlp_program_reset", "vlp_step", "vlp_program_run", "vlp_program_counts",
     "vlp_plan_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
     "vlp_profile_enable", "vlp_profile_read",
@@ -85,6 +85,7 @@ def lib():
             "vlp_keyswitch": (ctypes.c_int, [vp, vp, vp, vp, sz]),
             "vlp_gate": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp, vp, vp, sz]),
             "vlp_evaluate": (ctypes.c_int, [vp, vp, P(vlp_shape), vp, vp, vp, vp, vp]),
+            "vlp_server_encrypt": (ctypes.c_int, [vp, P(vlp_shape), vp, vp, vp, vp, vp, vp]),
             "vlp_program_create": (ctypes.c_int, [vp, vp, P(vlp_shape), vp, vp, vp, vp, vp, P(vp)]),
             "vlp_program_reset": (ctypes.c_int, [vp]),
             "vlp_step": (ctypes.c_int, [vp, P(vp), sz, P(sz)]),
@@ -195,6 +196,12 @@ def vlp_evaluate(ctx, ks, shape: vlp_shape, query_dev, db_loc_dev, db_pay_dev, R
                                    _ptr(db_pay_dev), _ptr(R_dev), _ptr(v_out_dev)))
 
 
+def vlp_server_encrypt(ctx, shape: vlp_shape, pk_loc_dev, pk_pay_dev, loc_dev, pay_dev, out_loc_dev,
+                       out_pay_dev) -> None:
+    _check(ctx, lib().vlp_server_encrypt(ctx, ctypes.byref(shape), _ptr(pk_loc_dev), _ptr(pk_pay_dev), _ptr(loc_dev),
+                                         _ptr(pay_dev), _ptr(out_loc_dev), _ptr(out_pay_dev)))
+
+
 def vlp_program_create(ctx, ks, shape: vlp_shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev):
     out = ctypes.c_void_p()
     _check(ctx, lib().vlp_program_create(ctx, ks, ctypes.byref(shape), _ptr(query_dev), _ptr(db_loc_dev),
@@ -296,6 +303,20 @@ class Context:
         """Host array of uint32 words -> int32 tensor on the device."""
         import numpy as np
         a = np.ascontiguousarray(np.asarray(arr, dtype=np.uint32)).view(np.int32)
+        with self.torch.cuda.stream(self.stream):
+            t = self.torch.from_numpy(a).to(self.device)
+        self.stream.synchronize()
+        return t
+
+    def array(self, arr):
+        """Host array of any fixed-width dtype -> tensor on the device with the
+        same bytes (uint64 travels as int64, uint32 as int32)."""
+        import numpy as np
+        a = np.ascontiguousarray(arr)
+        if a.dtype == np.uint64:
+            a = a.view(np.int64)
+        elif a.dtype == np.uint32:
+            a = a.view(np.int32)
         with self.torch.cuda.stream(self.stream):
             t = self.torch.from_numpy(a).to(self.device)
         self.stream.synchronize()

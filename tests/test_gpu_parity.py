@@ -156,3 +156,28 @@ def test_step_merges_programs(gpu, oracle_keys):
         assert np.array_equal(ctx.to_host(v), vw) and np.array_equal(ctx.to_host(R), Rw)
     for p in progs:
         vlp.vlp_program_destroy(ctx.ctx, p)
+
+
+@pytest.mark.parametrize("waves,blocks", [(1, 4), (2, 2), (4, 1), (8, 1)])
+def test_bootstrap_parity_every_launch_shape(gpu, oracle_keys, waves, blocks):
+    """Each blind-rotation workgroup shape (the 8-wave one has its own register
+    plan: key read at use, 32-bit accumulators) matches the oracle word for word;
+    41 items leave the last workgroup partly idle."""
+    vlp, ctx, ks = gpu
+    B = 41
+    ins = _rand_words(11, (B, O.n + 1))
+    masks, noise = synth.lwe_randomness(12, "shape", 3)
+    ins[:3] = O.encrypt_bits(oracle_keys, np.array([1, 0, 1]), masks, noise)
+    d_in = ctx.tensor(ins)
+    d_out = ctx.empty(B, O.N + 1)
+    old = vlp.vlp_get_tuning(ctx.ctx)
+    try:
+        vlp.vlp_set_tuning(ctx.ctx, waves, blocks, old.ks_gates_per_block)
+        vlp.vlp_bootstrap(ctx.ctx, ks, d_in, d_out, MU, B)
+        ctx.sync()
+    finally:
+        vlp.vlp_set_tuning(ctx.ctx, old.br_waves_per_block, old.br_blocks_per_cu, old.ks_gates_per_block)
+    got = ctx.to_host(d_out)
+    want = _pool(lambda c: O.bootstrap_wo_ks(oracle_keys, c, MU), list(ins))
+    for b in range(B):
+        assert np.array_equal(got[b], want[b]), (waves, blocks, b)
