@@ -129,13 +129,20 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
 #pragma unroll 1
       for (int c = 0; c < 2; ++c) {
         const uint32_t* poly = acc + c * RING_N;
-        uint32_t D[16];  // X^ab p - p, plus the rounding offset of the decomposition
+        // D = X^ab p - p, plus the rounding offset of the decomposition.  All 32
+        // reads are issued before the first use (one LDS round trip).
+        uint32_t D[16], src[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t j = r * 64 + lane;
-          const uint32_t s = (j + 2048u - ab) & 2047u;  // coefficient j of X^ab p is +-p[j - ab]
-          const uint32_t src = poly[s & 1023u];
-          D[r] = (s >= 1024u ? 0u - src : src) - poly[j] + DEC_OFFSET;
+          src[r] = poly[((j + 2048u - ab) & 2047u) & 1023u];  // coefficient j of X^ab p is +-p[j - ab]
+          D[r] = poly[j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
+          D[r] = (s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET;
         }
 #pragma unroll 1
         for (int lev = 0; lev < ELL; ++lev) {
@@ -197,8 +204,12 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
         }
         ntt_inv(v, buf, s_tw, tw_fwd, lane);
         uint32_t* poly = acc + c * RING_N;
+        uint32_t old[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) poly[r * 64 + lane] += crt_lift_u32(csub(v.a[r], P1), csub(v.b[r], P2));
+        for (int r = 0; r < 16; ++r) old[r] = poly[r * 64 + lane];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) poly[r * 64 + lane] = old[r] + crt_lift_u32(csub(v.a[r], P1), csub(v.b[r], P2));
       }
     }
     wave_lds_sync();

@@ -80,24 +80,38 @@ __device__ __forceinline__ void bfly_gs_neg(uint32_t& x, uint32_t& y, uint32_t w
   y = shoup(v - u + 2 * p, w, wp, p);
 }
 
+// The eight butterflies of a stage: register r (bit RB clear) pairs with
+// r | 2^RB.  All twiddle reads of the stage are issued before the first
+// butterfly (the scheduling barrier keeps the compiler from sinking them to
+// their uses), so the stage waits for one LDS round trip, not one per read.
+template <int RB>
+__device__ __forceinline__ constexpr int bfly_reg(int k) {
+  return ((k >> RB) << (RB + 1)) | (k & ((1 << RB) - 1));
+}
 template <int S, int (*LAY)(int, int), int RB>
 __device__ __forceinline__ void fwd_stage(Poly2& v, const Tw* tw, int lane) {
+  Tw w[8];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    if (r & (1 << RB)) continue;
-    const Tw w = tw[(1 << S) + (LAY(lane, r) >> (10 - S))];
-    bfly_ct<S == 0>(v.a[r], v.a[r | (1 << RB)], w.x, w.y, P1);
-    bfly_ct<S == 0>(v.b[r], v.b[r | (1 << RB)], w.z, w.w, P2);
+  for (int k = 0; k < 8; ++k) w[k] = tw[(1 << S) + (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int r = bfly_reg<RB>(k);
+    bfly_ct<S == 0>(v.a[r], v.a[r | (1 << RB)], w[k].x, w[k].y, P1);
+    bfly_ct<S == 0>(v.b[r], v.b[r | (1 << RB)], w[k].z, w[k].w, P2);
   }
 }
 template <int S, int (*LAY)(int, int), int RB>
 __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
+  Tw w[8];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    if (r & (1 << RB)) continue;
-    const Tw w = tw[(2 << S) - 1 - (LAY(lane, r) >> (10 - S))];
-    bfly_gs_neg(v.a[r], v.a[r | (1 << RB)], w.x, w.y, P1);
-    bfly_gs_neg(v.b[r], v.b[r | (1 << RB)], w.z, w.w, P2);
+  for (int k = 0; k < 8; ++k) w[k] = tw[(2 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int r = bfly_reg<RB>(k);
+    bfly_gs_neg(v.a[r], v.a[r | (1 << RB)], w[k].x, w[k].y, P1);
+    bfly_gs_neg(v.b[r], v.b[r | (1 << RB)], w[k].z, w[k].w, P2);
   }
 }
 
