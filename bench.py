@@ -4,8 +4,9 @@
 One step = one full pass of the hot path over one query: the 16-bit
 two-dimensional interval validation of 1,024 records (4 comparators and 3
 ANDs per record: 199,680 blind rotations, 134,144 key switches, 19 circuit
-levels), every level a batched blind-rotation launch plus a batched
-key-switching launch.  Inputs are resident in device memory before timing.
+levels), every level launched as rounds of 1,024 blind rotations (two
+wavefronts each, one per prime) plus one batched key-switching launch.
+Inputs are resident in device memory before timing.
 
 Prints one JSON line: blind rotations per second (value), the plain
 one-gate-per-launch rate on the same GPU, per-query latency percentiles,
@@ -41,10 +42,13 @@ OPS_PER_MODMUL = 16
 PEAK_MODMUL = VALU_LANE_OPS / OPS_PER_MODMUL  # 2.4576e12 modmul/s
 
 # A workload is one or more programs run together (their levels merged).
-# HBM-side traffic of br_kernel per launch on the default workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; copy-calibrated), valid only
-# for the kernel sources it was measured on (their sha256 prefix).
-TRAFFIC_MEASURED = {"kernel_sha": "fa9ed71a08e556b7", "bytes_per_launch": 5.16634e+08}
+# HBM-side traffic of the blind-rotation kernel per launch on the default
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE;
+# copy-calibrated), valid only for the kernel sources it was measured on
+# (their sha256 prefix) and the launch shape it was measured with.
+TRAFFIC_MEASURED = {"kernel_sha": "fa9ed71a08e556b7", "bytes_per_launch": 5.16634e+08,
+                    "launch": {"br_prime_split": 0, "br_waves_per_block": 4, "br_blocks_per_cu": 1,
+                               "ks_gates_per_block": 4}}
 KERNEL_SOURCES = ("kernels.hip", "wave_ntt.h", "rns.h", "vlp_api.cpp")
 
 
@@ -294,6 +298,8 @@ def main():
     ap.add_argument("--tuned", action="store_true", help="apply the cached autotuner result")
     ap.add_argument("--br-waves", type=int, default=0, help="waves per blind-rotation workgroup (1, 2, 4, 8)")
     ap.add_argument("--br-blocks", type=int, default=0, help="blind-rotation workgroups per CU the grid is sized for")
+    ap.add_argument("--br-split", type=int, default=-1, choices=(-1, 0, 1),
+                    help="1: two wavefronts per blind rotation, one per prime; 0: one wavefront")
     ap.add_argument("--serve", action="store_true", help="run the serving experiment instead")
     ap.add_argument("--table3", action="store_true", help="replay the paper's dataset shapes instead")
     ap.add_argument("--server-enc", action="store_true", help="time ServerEnc of a 65,536-record database instead")
@@ -346,13 +352,13 @@ def main():
     if args.tuned:
         from paper_2506_12761_amd import autotune
         log("cached tuning applied: %s" % autotune.load_cached(ctx, args.workload))
-    if args.br_waves or args.br_blocks:
+    if args.br_waves or args.br_blocks or args.br_split >= 0:
         t = vlp.vlp_get_tuning(ctx.ctx)
         vlp.vlp_set_tuning(ctx.ctx, args.br_waves or t.br_waves_per_block, args.br_blocks or t.br_blocks_per_cu,
-                           t.ks_gates_per_block)
+                           t.ks_gates_per_block, args.br_split if args.br_split >= 0 else t.br_prime_split)
     t = vlp.vlp_get_tuning(ctx.ctx)
-    launch = {"br_waves_per_block": t.br_waves_per_block, "br_blocks_per_cu": t.br_blocks_per_cu,
-              "ks_gates_per_block": t.ks_gates_per_block}
+    launch = {"br_prime_split": t.br_prime_split, "br_waves_per_block": t.br_waves_per_block,
+              "br_blocks_per_cu": t.br_blocks_per_cu, "ks_gates_per_block": t.ks_gates_per_block}
     progs, keep = [], []
     for k, p in enumerate(specs):
         mode, M, l, lS, d = p["mode"], p["M"], p["l"], p["lS"], p["d"]
@@ -441,12 +447,14 @@ def main():
         per_launch = MODMUL_PER_BR * br["items"] / br["launches"]
         achieved = per_launch / (avg_ms * 1e-3)
         traffic = None
-        if args.workload == "intv-1024" and TRAFFIC_MEASURED["kernel_sha"] == kernel_sha():
+        if (args.workload == "intv-1024" and TRAFFIC_MEASURED["kernel_sha"] == kernel_sha()
+                and TRAFFIC_MEASURED["launch"] == launch):
             traffic = TRAFFIC_MEASURED["bytes_per_launch"]
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MODMUL / 1e12,
                     "unit": "Tmodmul/s", "frac": achieved / PEAK_MODMUL, "traffic": traffic,
                     "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": alg_bytes,
-                    "kernel": "br_kernel", "launches": br["launches"], "avg_launch_ms": avg_ms,
+                    "kernel": "br2_kernel" if launch["br_prime_split"] else "br_kernel",
+                    "launches": br["launches"], "avg_launch_ms": avg_ms,
                     "ks_kernel_ms_share": prof["ks"]["ms"] / max(1e-9, prof["ks"]["ms"] + br["ms"])}
 
     cpu = None

@@ -207,14 +207,21 @@ vlp_status vlp_program_counts(const vlp_program *prog, uint64_t *gates, uint64_t
 vlp_status vlp_program_destroy(vlp_program *prog);
 
 /* ---- Tuning knobs of the batched kernels (picked by the autotuner).
- * br_waves_per_block: waves per workgroup of the blind-rotation kernel (1, 2, 4, 8;
- *                     8 = two per SIMD at half the registers each)
- * br_blocks_per_cu  : resident workgroups per compute unit the grid is sized for
- * ks_gates_per_block: gates sharing one pass over the key-switching key */
+ * br_prime_split    : 1 = two wavefronts per blind rotation, one per RNS
+ *                     prime, one rotation per workgroup (two wavefronts per
+ *                     SIMD); 0 = one wavefront per rotation
+ * br_waves_per_block: (split = 0) wavefronts per workgroup of the
+ *                     blind-rotation kernel (1, 2, 4, 8; 8 = two per SIMD at
+ *                     half the registers each)
+ * br_blocks_per_cu  : resident workgroups per compute unit the grid is sized
+ *                     for (1..64); one launch covers that many rotations per
+ *                     CU times the rotations per workgroup
+ * ks_gates_per_block: gates sharing one pass over the key-switching key (4, 8, 16) */
 typedef struct {
     uint32_t br_waves_per_block;
     uint32_t br_blocks_per_cu;
     uint32_t ks_gates_per_block;
+    uint32_t br_prime_split;
 } vlp_tuning;
 vlp_status vlp_get_tuning(const vlp_ctx *ctx, vlp_tuning *t);
 vlp_status vlp_set_tuning(vlp_ctx *ctx, const vlp_tuning *t);

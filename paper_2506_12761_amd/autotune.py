@@ -1,8 +1,9 @@
 """Autotuner for the batched kernels' launch shape, with a JSON cache.
 
 Two sweeps:
-  * launch shape -- waves per blind-rotation workgroup, workgroups per CU the
-    persistent grid is sized for, gates per key-switching workgroup -- timed
+  * launch shape -- one or two wavefronts per blind rotation, waves per
+    blind-rotation workgroup, workgroups per CU a launch is sized for, gates
+    per key-switching workgroup -- timed
     on a caller-supplied program (one full pass each), the fastest is set on
     the context and cached per device and workload;
   * batch size -- blind rotations per launch from 256 to 16,384, timed with
@@ -19,8 +20,14 @@ from . import vlp
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
-SHAPES = [(w, b, k) for w in (1, 2, 4, 8) for b in (1, 2, 4) for k in (4, 8, 16)
-          if w * b <= 8]
+# (split, waves per workgroup, workgroups per CU, gates per key-switching workgroup)
+SHAPES = ([(0, w, b, k) for w in (1, 2, 4, 8) for b in (1, 2, 4) for k in (4, 8, 16) if w * b <= 8]
+          + [(1, 1, b, k) for b in (2, 4, 8) for k in (4, 8, 16)])
+
+
+def _apply(ctx, best: dict) -> None:
+    vlp.vlp_set_tuning(ctx.ctx, best["br_waves_per_block"], best["br_blocks_per_cu"], best["ks_gates_per_block"],
+                       best.get("br_prime_split", 0))
 
 
 def _time_program(ctx, prog) -> float:
@@ -35,14 +42,15 @@ def _time_program(ctx, prog) -> float:
 def tune_launch(ctx, prog, shapes=SHAPES, log=None) -> dict:
     """Times `prog` under each launch shape; sets and returns the best."""
     results = []
-    for (w, b, k) in shapes:
-        vlp.vlp_set_tuning(ctx.ctx, w, b, k)
+    for (sp, w, b, k) in shapes:
+        vlp.vlp_set_tuning(ctx.ctx, w, b, k, sp)
         dt = _time_program(ctx, prog)
-        results.append({"br_waves_per_block": w, "br_blocks_per_cu": b, "ks_gates_per_block": k, "s": dt})
+        results.append({"br_prime_split": sp, "br_waves_per_block": w, "br_blocks_per_cu": b,
+                        "ks_gates_per_block": k, "s": dt})
         if log:
-            log("tune w=%d b=%d k=%d: %.3f s" % (w, b, k, dt))
+            log("tune split=%d w=%d b=%d k=%d: %.3f s" % (sp, w, b, k, dt))
     best = min(results, key=lambda r: r["s"])
-    vlp.vlp_set_tuning(ctx.ctx, best["br_waves_per_block"], best["br_blocks_per_cu"], best["ks_gates_per_block"])
+    _apply(ctx, best)
     return {"best": best, "all": results}
 
 
@@ -81,7 +89,7 @@ def load_cached(ctx, workload: str) -> bool:
         best = data[device_key()][workload]["best"]
     except (KeyError, ValueError, OSError):
         return False
-    vlp.vlp_set_tuning(ctx.ctx, best["br_waves_per_block"], best["br_blocks_per_cu"], best["ks_gates_per_block"])
+    _apply(ctx, best)
     return True
 
 

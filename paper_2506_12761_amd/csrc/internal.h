@@ -22,7 +22,8 @@ constexpr uint32_t MU = 0x20000000u; // 1/8
 // pairs (mod P1, mod P2), each polynomial in the NTT's transform order
 // (layout C, stored as [r][lane] so a wave's loads are contiguous), scaled
 // by 1/1024 and kept in Montgomery form (times 2^32 mod P).
-constexpr size_t BK_NTT_WORDS = (size_t)LWE_n * 2 * ELL * 2 * RING_N;  // uint2 entries
+constexpr size_t BK_ROW_WORDS = (size_t)2 * ELL * 2 * 2 * RING_N;  // one key row i: [6][2][2 primes][1024] words
+constexpr size_t BK_NTT_WORDS = (size_t)LWE_n * BK_ROW_WORDS;
 // Re-laid key-switching key: [1024][8][3 digits 1..3][640] words.
 constexpr size_t KSK_WORDS = (size_t)RING_N * KS_T * 3 * KS_ROW;       // u32 words
 
@@ -32,7 +33,7 @@ struct BrItem {
   const uint32_t* a;
   const uint32_t* b;    // may be null (then cb is ignored)
   uint32_t* out;        // [1025]
-  const uint2* bk;      // transformed bootstrapping key
+  const uint32_t* bk;   // transformed bootstrapping key
   int32_t ca, cb;
   uint32_t cst, mu;
 };
@@ -49,16 +50,18 @@ struct KsItem {
 
 // Host-side launchers (kernels.hip).  All enqueue on `stream` and return the
 // HIP error of the launch.
-int launch_bk_transform(const uint32_t* bk_coeff, uint2* bk_ntt, const uint4* tw_fwd, void* stream);
+int launch_bk_transform(const uint32_t* bk_coeff, uint32_t* bk_ntt, const uint4* tw_fwd, void* stream);
 int launch_ksk_relayout(const uint32_t* ksk_in, uint32_t* ksk_out, void* stream);
 int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t waves_per_block, uint32_t blocks,
               void* stream);
 // ServerEnc over a flat [count][631] array; out == pk runs in place.
 int launch_server_enc(const uint32_t* pk, uint32_t* out, size_t count, const int64_t* vals, const uint8_t* bytes,
                       uint32_t l, void* stream);
+// Two wavefronts per rotation (one per prime), one rotation per workgroup.
+int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream);
 int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream);
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
-                         uint32_t cst, uint32_t mu, uint32_t* out, const uint2* bk, void* stream);
+                         uint32_t cst, uint32_t mu, uint32_t* out, const uint32_t* bk, void* stream);
 int launch_make_ks_items(KsItem* items, uint32_t count, const uint32_t* u1, const uint32_t* u2, uint32_t cst,
                          uint32_t* out, const uint32_t* ksk, void* stream);
 int launch_negate(const uint32_t* a, uint32_t* out, size_t words, void* stream);

@@ -19,7 +19,7 @@ namespace vlp {
 // 2^32 / 1024 (mod P_k), canonical again.
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t* __restrict__ bk_coeff,
-                                                                   uint2* __restrict__ bk_ntt,
+                                                                   uint32_t* __restrict__ bk_ntt,
                                                                    const Tw* __restrict__ tw_fwd,
                                                                    uint32_t n_polys, uint4 scale) {
   __shared__ Tw s_tw[RING_N];
@@ -38,11 +38,12 @@ __global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t
       v.b[r] = x % P2;
     }
     ntt_fwd(v, s_buf[wave], s_tw, tw_fwd, lane);
-    uint2* dst = bk_ntt + (size_t)poly * RING_N;
+    uint32_t* dst = bk_ntt + (size_t)poly * 2 * RING_N;  // plane of P1, then plane of P2
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const uint32_t a = csub(csub(v.a[r], 2 * P1), P1), b = csub(csub(v.b[r], 2 * P2), P2);
-      dst[r * 64 + lane] = make_uint2(csub(shoup(a, scale.x, scale.y, P1), P1), csub(shoup(b, scale.z, scale.w, P2), P2));
+      dst[r * 64 + lane] = csub(shoup(a, scale.x, scale.y, P1), P1);
+      dst[RING_N + r * 64 + lane] = csub(shoup(b, scale.z, scale.w, P2), P2);
     }
   }
 }
@@ -65,7 +66,6 @@ constexpr uint32_t DEC_OFFSET = (1u << 31) + (1u << 24) + (1u << 17) + (1u << 10
 
 // Global-address-space views: loads through them are global (not flat)
 // loads, so they are not counted by the LDS wait of the transposes.
-typedef const uint64_t __attribute__((address_space(1))) g_u64;
 typedef const uint32_t __attribute__((address_space(1))) g_u32;
 
 // Up to 4 wavefronts per workgroup (one per SIMD) a wavefront may hold 512
@@ -112,8 +112,8 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
       acc[j] = 0;
       acc[RING_N + j] = neg ? (0u - I.mu) : I.mu;
     }
-    const uint2* bk_i = I.bk;
-    for (int i = 0; i < LWE_n; ++i, bk_i += 2 * ELL * 2 * RING_N) {
+    const uint32_t* bk_i = I.bk;
+    for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
       const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
       if (ab == 0) continue;
       // External product BK_i x (X^ab acc - acc): the six digit polynomials are
@@ -146,16 +146,19 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
         }
 #pragma unroll 1
         for (int lev = 0; lev < ELL; ++lev) {
-          // {residue mod P1 (low word), residue mod P2 (high word)} of the two key
-          // rows of this digit; with registers to spare they are requested before
-          // the transform, which hides their latency.
-          const g_u64* k0 = (const g_u64*)(bk_i + (size_t)((c * ELL + lev) * 2) * RING_N);
-          uint64_t b0[16], b1[16];
+          // Residues mod P1 and mod P2 of the two key rows of this digit (planes
+          // of 1,024 words: row 0 P1, row 0 P2, row 1 P1, row 1 P2); with
+          // registers to spare they are requested before the transform, which
+          // hides their latency.
+          const g_u32* k0 = (const g_u32*)(bk_i + (size_t)((c * ELL + lev) * 4) * RING_N);
+          uint32_t b0a[16], b0b[16], b1a[16], b1b[16];
           if constexpr (kPrefetchKey) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              b0[r] = k0[r * 64 + lane];
-              b1[r] = k0[RING_N + r * 64 + lane];
+              b0a[r] = k0[r * 64 + lane];
+              b0b[r] = k0[RING_N + r * 64 + lane];
+              b1a[r] = k0[2 * RING_N + r * 64 + lane];
+              b1b[r] = k0[3 * RING_N + r * 64 + lane];
             }
           }
           const int shift = 32 - BG_BIT * (lev + 1);
@@ -170,21 +173,23 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             if constexpr (!kPrefetchKey) {
-              b0[r] = k0[r * 64 + lane];
-              b1[r] = k0[RING_N + r * 64 + lane];
+              b0a[r] = k0[r * 64 + lane];
+              b0b[r] = k0[RING_N + r * 64 + lane];
+              b1a[r] = k0[2 * RING_N + r * 64 + lane];
+              b1b[r] = k0[3 * RING_N + r * 64 + lane];
             }
             if constexpr (kWideAcc) {
               const uint32_t da = csub(csub(v.a[r], 2 * P1), P1), db = csub(csub(v.b[r], 2 * P2), P2);  // [0, P)
-              m0a[r] += (uint64_t)da * (uint32_t)b0[r];
-              m0b[r] += (uint64_t)db * (uint32_t)(b0[r] >> 32);
-              m1a[r] += (uint64_t)da * (uint32_t)b1[r];
-              m1b[r] += (uint64_t)db * (uint32_t)(b1[r] >> 32);
+              m0a[r] += (uint64_t)da * b0a[r];
+              m0b[r] += (uint64_t)db * b0b[r];
+              m1a[r] += (uint64_t)da * b1a[r];
+              m1b[r] += (uint64_t)db * b1b[r];
             } else {
               const uint32_t da = csub(v.a[r], 2 * P1), db = csub(v.b[r], 2 * P2);  // [0, 2P)
-              m0a[r] += redc((uint64_t)da * (uint32_t)b0[r], P1, P1_INV);
-              m0b[r] += redc((uint64_t)db * (uint32_t)(b0[r] >> 32), P2, P2_INV);
-              m1a[r] += redc((uint64_t)da * (uint32_t)b1[r], P1, P1_INV);
-              m1b[r] += redc((uint64_t)db * (uint32_t)(b1[r] >> 32), P2, P2_INV);
+              m0a[r] += redc((uint64_t)da * b0a[r], P1, P1_INV);
+              m0b[r] += redc((uint64_t)db * b0b[r], P2, P2_INV);
+              m1a[r] += redc((uint64_t)da * b1a[r], P1, P1_INV);
+              m1b[r] += redc((uint64_t)db * b1b[r], P2, P2_INV);
             }
           }
         }
@@ -222,6 +227,149 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
       else I.out[RING_N - j] = 0u - a;
     }
     if (lane == 0) I.out[RING_N] = acc[RING_N];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blind rotation split by prime: a workgroup of two wavefronts per item, wave
+// PR computing every product modulo prime PR.  Each wavefront needs about half
+// the registers of the one-wavefront form, so two fit on a SIMD and hide each
+// other's memory and LDS latency.  Per CMux the two meet twice: after the
+// inverse transforms (each hands the other the residues of the output
+// polynomial that the other lifts) and after the accumulator update.
+// ---------------------------------------------------------------------------
+template <int PR>
+__device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const uint16_t* abar, uint32_t* buf,
+                                           const uint32_t* other_buf, const uint2* tw2, const uint2* gtw2, int lane) {
+  constexpr uint32_t P = Prime<PR>::P, PINV = Prime<PR>::PINV;
+  const uint32_t* bk_i = I.bk;
+  for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
+    const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
+    if (ab == 0) continue;  // the same decision in both wavefronts: abar is shared
+    // 64-bit accumulators of the two output polynomials mod P: canonical
+    // residues keep six products below P * 2^32 (one reduction at the end).
+    uint64_t m0[16], m1[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t* poly = acc + c * RING_N;
+      uint32_t D[16], src[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t j = r * 64 + lane;
+        src[r] = poly[((j + 2048u - ab) & 2047u) & 1023u];  // coefficient j of X^ab p is +-p[j - ab]
+        D[r] = poly[j];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
+        D[r] = (s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET;
+      }
+#pragma unroll 1
+      for (int lev = 0; lev < ELL; ++lev) {
+        // This prime's planes of the two key rows of the digit, requested
+        // before the transform so that it hides their latency.
+        const g_u32* k0 = (const g_u32*)(bk_i + (size_t)((c * ELL + lev) * 4 + PR) * RING_N);
+        uint32_t b0[16], b1[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          b0[r] = k0[r * 64 + lane];
+          b1[r] = k0[2 * RING_N + r * 64 + lane];
+        }
+        const int shift = 32 - BG_BIT * (lev + 1);
+        uint32_t x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = res_of((int32_t)((D[r] >> shift) & 127u) - 64, P);
+        ntt_fwd1<PR>(x, buf, tw2, gtw2, lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const uint32_t d = csub(csub(x[r], 2 * P), P);  // [0, P)
+          m0[r] += (uint64_t)d * b0[r];
+          m1[r] += (uint64_t)d * b1[r];
+        }
+      }
+    }
+    // Wave 0 lifts output 0 (A), wave 1 output 1 (B).  The kept output is
+    // transformed first and stays in registers; the other one is transformed
+    // next and parked in this wavefront's LDS buffer for the partner.
+    constexpr int KEEP = PR;
+    uint32_t keep[16], x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = redc(KEEP ? m1[r] : m0[r], P, PINV);
+    ntt_inv1<PR>(x, buf, tw2, gtw2, lane);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      keep[r] = csub(x[r], P);
+      x[r] = redc(KEEP ? m0[r] : m1[r], P, PINV);
+    }
+    ntt_inv1<PR>(x, buf, tw2, gtw2, lane);
+    wave_lds_sync();  // the transform's last reads of buf are done
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[r * 64 + lane] = csub(x[r], P);
+    __syncthreads();  // both wavefronts have parked their residues
+    uint32_t* poly = acc + KEEP * RING_N;
+    uint32_t old[16], oth[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      old[r] = poly[r * 64 + lane];
+      oth[r] = other_buf[r * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      poly[r * 64 + lane] = old[r] + (PR == 0 ? crt_lift_u32(keep[r], oth[r]) : crt_lift_u32(oth[r], keep[r]));
+    __syncthreads();  // accumulator updated; parked residues consumed
+  }
+}
+
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void br2_kernel(const BrItem* __restrict__ items, uint32_t count,
+                                                  const Tw* __restrict__ tw_fwd) {
+  __shared__ Tw s_tw[RING_N];                  // twiddles of both primes (16 KB)
+  __shared__ uint32_t s_buf[2][RING_N];        // per wavefront: transpose scratch, then parked residues
+  __shared__ uint32_t s_acc[2][RING_N];        // accumulator (A, B), coefficient order
+  __shared__ uint16_t s_abar[CT_n + 1];        // modulus-switched input
+  for (int k = threadIdx.x; k < RING_N; k += blockDim.x) s_tw[k] = tw_fwd[k];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint2* tw2 = reinterpret_cast<const uint2*>(s_tw);
+  const uint2* gtw2 = reinterpret_cast<const uint2*>(tw_fwd);
+  uint32_t* acc = s_acc[0];
+  for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const BrItem I = items[it];
+    __syncthreads();  // the previous item's readers of acc and abar are done
+    const g_u32* in_a = (const g_u32*)I.a;
+    const g_u32* in_b = (const g_u32*)I.b;
+    for (int w = threadIdx.x; w < CT_n; w += 128) {
+      uint32_t x = (uint32_t)I.ca * in_a[w];
+      if (I.b) x += (uint32_t)I.cb * in_b[w];
+      if (w == LWE_n) x += I.cst;
+      s_abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
+    }
+    __syncthreads();
+    // acc = (0, X^(-bbar) * mu * (1 + X + ... + X^1023)): wave 0 writes A, wave 1 B.
+    const uint32_t bbar = __builtin_amdgcn_readfirstlane(s_abar[LWE_n]);
+    const uint32_t rot = (2048u - bbar) & 2047u;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t j = r * 64 + lane;
+      const bool neg = (j < (rot & 1023u)) != (rot >= 1024u);
+      acc[wave * RING_N + j] = wave == 0 ? 0u : (neg ? (0u - I.mu) : I.mu);
+    }
+    __syncthreads();
+    if (wave == 0)
+      br2_rotate<0>(I, acc, s_abar, s_buf[0], s_buf[1], tw2, gtw2, lane);
+    else
+      br2_rotate<1>(I, acc, s_abar, s_buf[1], s_buf[0], tw2, gtw2, lane);
+    // SampleExtract: a'_0 = A_0, a'_j = -A_(N-j), b' = B_0 (the last update is
+    // visible after the rotation's closing barrier, or the one above if no step ran).
+    for (int j = threadIdx.x; j < RING_N; j += 128) {
+      const uint32_t a = acc[j];
+      if (j == 0) I.out[0] = a;
+      else I.out[RING_N - j] = 0u - a;
+    }
+    if (threadIdx.x == 0) I.out[RING_N] = acc[RING_N];
   }
 }
 
@@ -294,7 +442,7 @@ __global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict
 // Helpers
 // ---------------------------------------------------------------------------
 __global__ void make_br_items_kernel(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca,
-                                     int32_t cb, uint32_t cst, uint32_t mu, uint32_t* out, const uint2* bk) {
+                                     int32_t cb, uint32_t cst, uint32_t mu, uint32_t* out, const uint32_t* bk) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   BrItem it;
@@ -395,7 +543,7 @@ __global__ void server_enc_inplace_kernel(uint32_t* ct, size_t count, const int6
 // ---------------------------------------------------------------------------
 static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-int launch_bk_transform(const uint32_t* bk_coeff, uint2* bk_ntt, const uint4* tw_fwd, void* stream) {
+int launch_bk_transform(const uint32_t* bk_coeff, uint32_t* bk_ntt, const uint4* tw_fwd, void* stream) {
   const uint32_t n_polys = LWE_n * 2 * ELL * 2;
   uint32_t sc[4];
   key_scale(sc);
@@ -425,6 +573,13 @@ int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t
   return (int)hipGetLastError();
 }
 
+int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream) {
+  if (count == 0) return 0;
+  if (blocks == 0 || blocks > count) blocks = count;
+  hipLaunchKernelGGL(br2_kernel, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd);
+  return (int)hipGetLastError();
+}
+
 int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream) {
   if (count == 0) return 0;
   switch (gates_per_block) {
@@ -443,7 +598,7 @@ int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, ui
 }
 
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
-                         uint32_t cst, uint32_t mu, uint32_t* out, const uint2* bk, void* stream) {
+                         uint32_t cst, uint32_t mu, uint32_t* out, const uint32_t* bk, void* stream) {
   if (count == 0) return 0;
   hipLaunchKernelGGL(make_br_items_kernel, dim3((count + 255) / 256), dim3(256), 0, S(stream), items, count, a, b, ca,
                      cb, cst, mu, out, bk);

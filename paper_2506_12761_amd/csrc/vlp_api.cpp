@@ -24,7 +24,7 @@ struct vlp_ctx {
   std::string err;
   uint4* tw_fwd = nullptr;  // device twiddle table
   int num_cus = 256;
-  vlp_tuning tune{4, 1, 4};
+  vlp_tuning tune{4, 4, 4, 1};
   // Grow-only scratch for the elementwise calls.
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -39,7 +39,7 @@ struct vlp_ctx {
 
 struct vlp_keyset {
   vlp_ctx* ctx;
-  uint2* bk_ntt;
+  uint32_t* bk_ntt;
   uint32_t* ksk;
   int users;  // live programs made with it
 };
@@ -153,12 +153,14 @@ void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
 // re-fetch the key (measured: ~0.5 MB vs up to ~36 MB of key traffic per
 // blind rotation).
 int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
-  const uint32_t waves = ctx->tune.br_waves_per_block, blocks = (uint32_t)br_blocks(ctx);
-  const uint32_t chunk = blocks * waves;
+  const bool split = ctx->tune.br_prime_split != 0;
+  const uint32_t waves = split ? 1 : ctx->tune.br_waves_per_block, blocks = (uint32_t)br_blocks(ctx);
+  const uint32_t chunk = blocks * waves;  // rotations per launch
   for (uint32_t first = 0; first < count; first += chunk) {
     const uint32_t n = std::min(chunk, count - first);
     const int m = mark_begin(ctx);
-    const int e = launch_br(items + first, n, ctx->tw_fwd, waves, blocks, ctx->stream);
+    const int e = split ? launch_br2(items + first, n, ctx->tw_fwd, blocks, ctx->stream)
+                        : launch_br(items + first, n, ctx->tw_fwd, waves, blocks, ctx->stream);
     mark_end(ctx, m, 0, n);
     if (e != 0) return e;
   }
@@ -346,6 +348,7 @@ extern "C" vlp_status vlp_set_tuning(vlp_ctx* ctx, const vlp_tuning* t) {
   if (!(w == 1 || w == 2 || w == 4 || w == 8)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2, 4 or 8");
   if (t->br_blocks_per_cu < 1 || t->br_blocks_per_cu > 64) return fail(ctx, VLP_EINVAL, "br_blocks_per_cu out of [1, 64]");
   if (!(g == 4 || g == 8 || g == 16)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 4, 8 or 16");
+  if (t->br_prime_split > 1) return fail(ctx, VLP_EINVAL, "br_prime_split must be 0 or 1");
   ctx->tune = *t;
   return VLP_OK;
 }
@@ -358,17 +361,17 @@ extern "C" vlp_status vlp_keyset_load(vlp_ctx* ctx, const uint32_t* bk_dev, cons
   if (!bk_dev || !ksk_dev || !out) return fail(ctx, VLP_EINVAL, "null argument");
   *out = nullptr;
   vlp_keyset* ks = new vlp_keyset{ctx, nullptr, nullptr, 0};
-  vlp_status st = dev_alloc(ctx, (void**)&ks->bk_ntt, BK_NTT_WORDS * 8);
+  vlp_status st = dev_alloc(ctx, (void**)&ks->bk_ntt, BK_NTT_WORDS * 4);
   if (st == VLP_OK) st = dev_alloc(ctx, (void**)&ks->ksk, KSK_WORDS * 4);
   if (st != VLP_OK) {
-    dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 8);
+    dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 4);
     delete ks;
     return st;
   }
   int e = launch_bk_transform(bk_dev, ks->bk_ntt, ctx->tw_fwd, ctx->stream);
   if (e == 0) e = launch_ksk_relayout(ksk_dev, ks->ksk, ctx->stream);
   if (e != 0) {
-    dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 8);
+    dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 4);
     dev_free(ctx, ks->ksk, KSK_WORDS * 4);
     delete ks;
     return fail(ctx, VLP_EHIP, "key preparation launch: %s", hipGetErrorString((hipError_t)e));
@@ -393,7 +396,7 @@ extern "C" vlp_status vlp_keyset_destroy(vlp_keyset* ks) {
   }
   if (ks->users) return fail(ctx, VLP_EBUSY, "keyset still used by %d programs", ks->users);
   (void)hipStreamSynchronize(ctx->stream);
-  dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 8);
+  dev_free(ctx, ks->bk_ntt, BK_NTT_WORDS * 4);
   dev_free(ctx, ks->ksk, KSK_WORDS * 4);
   ctx->live_keysets--;
   delete ks;

@@ -150,4 +150,97 @@ __device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, cons
   inv_stage<0, lay_a, 3>(v, gtw, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Single-prime form: one wavefront transforms the residues of one prime
+// (two wavefronts per blind rotation).  Same stages, layouts and twiddle
+// table (entry e of prime PR is the uint2 at index 2e + PR of the table).
+// ---------------------------------------------------------------------------
+template <int PR>
+struct Prime;
+template <>
+struct Prime<0> {
+  static constexpr uint32_t P = P1, PINV = P1_INV;
+};
+template <>
+struct Prime<1> {
+  static constexpr uint32_t P = P2, PINV = P2_INV;
+};
+
+// LDS slot of element j for 4-byte transposes: 32 lanes of every layout hit
+// 32 distinct banks (h = j >> 6 goes to bank bits {0,1,4} and {2,3,4} alike).
+__device__ __forceinline__ int lds_slot1(int j) {
+  const int h = j >> 6;
+  return j ^ ((h & 3) | ((h & 3) << 2) | (((h >> 2) & 1) << 4) | (((h >> 3) & 1) << 5));
+}
+
+template <int (*FROM)(int, int), int (*TO)(int, int)>
+__device__ __forceinline__ void wave_transpose1(uint32_t (&x)[16], uint32_t* buf, int lane) {
+  wave_lds_sync();  // earlier readers of buf are done
+#pragma unroll
+  for (int r = 0; r < 16; ++r) buf[lds_slot1(FROM(lane, r))] = x[r];
+  wave_lds_sync();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) x[r] = buf[lds_slot1(TO(lane, r))];
+}
+
+template <int PR, int S, int (*LAY)(int, int), int RB>
+__device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tw2, int lane) {
+  uint2 w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = tw2[2 * ((1 << S) + (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))) + PR];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int r = bfly_reg<RB>(k);
+    bfly_ct<S == 0>(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
+  }
+}
+template <int PR, int S, int (*LAY)(int, int), int RB>
+__device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tw2, int lane) {
+  uint2 w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = tw2[2 * ((2 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))) + PR];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int r = bfly_reg<RB>(k);
+    bfly_gs_neg(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
+  }
+}
+
+// tw2 / gtw2: the LDS and global twiddle tables viewed as uint2 pairs.
+template <int PR>
+__device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const uint2* tw2,
+                                         const uint2* __restrict__ gtw2, int lane) {
+  fwd_stage1<PR, 0, lay_a, 3>(x, gtw2, lane);
+  fwd_stage1<PR, 1, lay_a, 2>(x, gtw2, lane);
+  fwd_stage1<PR, 2, lay_a, 1>(x, gtw2, lane);
+  fwd_stage1<PR, 3, lay_a, 0>(x, gtw2, lane);
+  wave_transpose1<lay_a, lay_b>(x, buf, lane);
+  fwd_stage1<PR, 4, lay_b, 3>(x, tw2, lane);
+  fwd_stage1<PR, 5, lay_b, 2>(x, tw2, lane);
+  fwd_stage1<PR, 6, lay_b, 1>(x, tw2, lane);
+  fwd_stage1<PR, 7, lay_b, 0>(x, tw2, lane);
+  wave_transpose1<lay_b, lay_c>(x, buf, lane);
+  fwd_stage1<PR, 8, lay_c, 1>(x, tw2, lane);
+  fwd_stage1<PR, 9, lay_c, 0>(x, tw2, lane);
+}
+
+template <int PR>
+__device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tw2,
+                                         const uint2* __restrict__ gtw2, int lane) {
+  inv_stage1<PR, 9, lay_c, 0>(x, tw2, lane);
+  inv_stage1<PR, 8, lay_c, 1>(x, tw2, lane);
+  wave_transpose1<lay_c, lay_b>(x, buf, lane);
+  inv_stage1<PR, 7, lay_b, 0>(x, tw2, lane);
+  inv_stage1<PR, 6, lay_b, 1>(x, tw2, lane);
+  inv_stage1<PR, 5, lay_b, 2>(x, tw2, lane);
+  inv_stage1<PR, 4, lay_b, 3>(x, tw2, lane);
+  wave_transpose1<lay_b, lay_a>(x, buf, lane);
+  inv_stage1<PR, 3, lay_a, 0>(x, gtw2, lane);
+  inv_stage1<PR, 2, lay_a, 1>(x, gtw2, lane);
+  inv_stage1<PR, 1, lay_a, 2>(x, gtw2, lane);
+  inv_stage1<PR, 0, lay_a, 3>(x, gtw2, lane);
+}
+
 }  // namespace vlp
