@@ -240,7 +240,7 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
 // ---------------------------------------------------------------------------
 template <int PR>
 __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const uint16_t* abar, uint32_t* buf,
-                                           const uint32_t* other_buf, const uint2* tw2, const uint2* gtw2, int lane) {
+                                           const uint32_t* other_buf, const uint2* tws, const uint2* gtw2, int lane) {
   constexpr uint32_t P = Prime<PR>::P, PINV = Prime<PR>::PINV;
   const uint32_t* bk_i = I.bk;
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
@@ -282,7 +282,7 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
         uint32_t x[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = res_of((int32_t)((D[r] >> shift) & 127u) - 64, P);
-        ntt_fwd1<PR>(x, buf, tw2, gtw2, lane);
+        ntt_fwd1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t d = csub(csub(x[r], 2 * P), P);  // [0, P)
@@ -298,13 +298,13 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     uint32_t keep[16], x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = redc(KEEP ? m1[r] : m0[r], P, PINV);
-    ntt_inv1<PR>(x, buf, tw2, gtw2, lane);
+    ntt_inv1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       keep[r] = csub(x[r], P);
       x[r] = redc(KEEP ? m0[r] : m1[r], P, PINV);
     }
-    ntt_inv1<PR>(x, buf, tw2, gtw2, lane);
+    ntt_inv1<PR>(x, buf, tws, gtw2, lane);
     wave_lds_sync();  // the transform's last reads of buf are done
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[r * 64 + lane] = csub(x[r], P);
@@ -326,14 +326,19 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
 
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void br2_kernel(const BrItem* __restrict__ items, uint32_t count,
                                                   const Tw* __restrict__ tw_fwd) {
-  __shared__ Tw s_tw[RING_N];                  // twiddles of both primes (16 KB)
+  __shared__ uint2 s_tw[2][RING_N];            // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
   __shared__ uint32_t s_buf[2][RING_N];        // per wavefront: transpose scratch, then parked residues
   __shared__ uint32_t s_acc[2][RING_N];        // accumulator (A, B), coefficient order
   __shared__ uint16_t s_abar[CT_n + 1];        // modulus-switched input
-  for (int k = threadIdx.x; k < RING_N; k += blockDim.x) s_tw[k] = tw_fwd[k];
+  for (int e = 16 + threadIdx.x; e < RING_N; e += blockDim.x) {  // stages 4..9 (entries 16..1023)
+    const int S = 31 - __builtin_clz(e);
+    const int slot = (1 << S) + tw_perm(S, e - (1 << S));
+    const Tw w = tw_fwd[e];
+    s_tw[0][slot] = make_uint2(w.x, w.y);
+    s_tw[1][slot] = make_uint2(w.z, w.w);
+  }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint2* tw2 = reinterpret_cast<const uint2*>(s_tw);
   const uint2* gtw2 = reinterpret_cast<const uint2*>(tw_fwd);
   uint32_t* acc = s_acc[0];
   for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
@@ -359,9 +364,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void b
     }
     __syncthreads();
     if (wave == 0)
-      br2_rotate<0>(I, acc, s_abar, s_buf[0], s_buf[1], tw2, gtw2, lane);
+      br2_rotate<0>(I, acc, s_abar, s_buf[0], s_buf[1], s_tw[0], gtw2, lane);
     else
-      br2_rotate<1>(I, acc, s_abar, s_buf[1], s_buf[0], tw2, gtw2, lane);
+      br2_rotate<1>(I, acc, s_abar, s_buf[1], s_buf[0], s_tw[1], gtw2, lane);
     // SampleExtract: a'_0 = A_0, a'_j = -A_(N-j), b' = B_0 (the last update is
     // visible after the rotation's closing barrier, or the one above if no step ran).
     for (int j = threadIdx.x; j < RING_N; j += 128) {

@@ -183,11 +183,30 @@ __device__ __forceinline__ void wave_transpose1(uint32_t (&x)[16], uint32_t* buf
   for (int r = 0; r < 16; ++r) x[r] = buf[lds_slot1(TO(lane, r))];
 }
 
+// Position of twiddle-table entry 2^S + o inside stage S's slice of a
+// per-prime LDS plane.  Stage S >= 4 reads entry offsets o whose bits hold the
+// lane group h = lane >> 2 (and, in layout C, q = lane & 3) above bits set by
+// the register index; the permutation moves the lane bits to the bottom, so
+// for every butterfly slot the 64 lanes read one contiguous run of entries
+// (no bank conflicts).  A bijection on [0, 2^S) for every S.
+__host__ __device__ __forceinline__ constexpr int tw_perm(int S, int o) {
+  return S < 4    ? o
+         : S <= 7 ? (((o & ((1 << (S - 4)) - 1)) << 4) | (o >> (S - 4)))                       // o = h | c
+         : S == 8 ? ((((o >> 2) & 3) << 6) | ((o >> 4) << 2) | (o & 3))                        // o = h | c | q
+                  : ((((o >> 3) & 3) << 7) | ((o & 1) << 6) | ((o >> 5) << 2) | ((o >> 1) & 3));  // o = h | c | q | d
+}
+
+// Stages 0..3 read the global table (wavefront-uniform: scalar loads), entry
+// e of prime PR at gtw2[2e + PR]; stages 4..9 read this prime's permuted LDS
+// plane tws.
 template <int PR, int S, int (*LAY)(int, int), int RB>
-__device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tw2, int lane) {
+__device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tws, const uint2* gtw2, int lane) {
   uint2 w[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = tw2[2 * ((1 << S) + (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))) + PR];
+  for (int k = 0; k < 8; ++k) {
+    const int o = LAY(lane, bfly_reg<RB>(k)) >> (10 - S);
+    w[k] = S < 4 ? gtw2[2 * ((1 << S) + o) + PR] : tws[(1 << S) + tw_perm(S, o)];
+  }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -196,10 +215,13 @@ __device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tw2, 
   }
 }
 template <int PR, int S, int (*LAY)(int, int), int RB>
-__device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tw2, int lane) {
+__device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tws, const uint2* gtw2, int lane) {
   uint2 w[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = tw2[2 * ((2 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))) + PR];
+  for (int k = 0; k < 8; ++k) {
+    const int o = (1 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S));  // entry 2^(S+1) - 1 - i
+    w[k] = S < 4 ? gtw2[2 * ((1 << S) + o) + PR] : tws[(1 << S) + tw_perm(S, o)];
+  }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -208,39 +230,39 @@ __device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tw2, 
   }
 }
 
-// tw2 / gtw2: the LDS and global twiddle tables viewed as uint2 pairs.
+// tws: this prime's permuted LDS plane; gtw2: the global table as uint2 pairs.
 template <int PR>
-__device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const uint2* tw2,
+__device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws,
                                          const uint2* __restrict__ gtw2, int lane) {
-  fwd_stage1<PR, 0, lay_a, 3>(x, gtw2, lane);
-  fwd_stage1<PR, 1, lay_a, 2>(x, gtw2, lane);
-  fwd_stage1<PR, 2, lay_a, 1>(x, gtw2, lane);
-  fwd_stage1<PR, 3, lay_a, 0>(x, gtw2, lane);
+  fwd_stage1<PR, 0, lay_a, 3>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
   wave_transpose1<lay_a, lay_b>(x, buf, lane);
-  fwd_stage1<PR, 4, lay_b, 3>(x, tw2, lane);
-  fwd_stage1<PR, 5, lay_b, 2>(x, tw2, lane);
-  fwd_stage1<PR, 6, lay_b, 1>(x, tw2, lane);
-  fwd_stage1<PR, 7, lay_b, 0>(x, tw2, lane);
+  fwd_stage1<PR, 4, lay_b, 3>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 5, lay_b, 2>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 6, lay_b, 1>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 7, lay_b, 0>(x, tws, gtw2, lane);
   wave_transpose1<lay_b, lay_c>(x, buf, lane);
-  fwd_stage1<PR, 8, lay_c, 1>(x, tw2, lane);
-  fwd_stage1<PR, 9, lay_c, 0>(x, tw2, lane);
+  fwd_stage1<PR, 8, lay_c, 1>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 9, lay_c, 0>(x, tws, gtw2, lane);
 }
 
 template <int PR>
-__device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tw2,
+__device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws,
                                          const uint2* __restrict__ gtw2, int lane) {
-  inv_stage1<PR, 9, lay_c, 0>(x, tw2, lane);
-  inv_stage1<PR, 8, lay_c, 1>(x, tw2, lane);
+  inv_stage1<PR, 9, lay_c, 0>(x, tws, gtw2, lane);
+  inv_stage1<PR, 8, lay_c, 1>(x, tws, gtw2, lane);
   wave_transpose1<lay_c, lay_b>(x, buf, lane);
-  inv_stage1<PR, 7, lay_b, 0>(x, tw2, lane);
-  inv_stage1<PR, 6, lay_b, 1>(x, tw2, lane);
-  inv_stage1<PR, 5, lay_b, 2>(x, tw2, lane);
-  inv_stage1<PR, 4, lay_b, 3>(x, tw2, lane);
+  inv_stage1<PR, 7, lay_b, 0>(x, tws, gtw2, lane);
+  inv_stage1<PR, 6, lay_b, 1>(x, tws, gtw2, lane);
+  inv_stage1<PR, 5, lay_b, 2>(x, tws, gtw2, lane);
+  inv_stage1<PR, 4, lay_b, 3>(x, tws, gtw2, lane);
   wave_transpose1<lay_b, lay_a>(x, buf, lane);
-  inv_stage1<PR, 3, lay_a, 0>(x, gtw2, lane);
-  inv_stage1<PR, 2, lay_a, 1>(x, gtw2, lane);
-  inv_stage1<PR, 1, lay_a, 2>(x, gtw2, lane);
-  inv_stage1<PR, 0, lay_a, 3>(x, gtw2, lane);
+  inv_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
+  inv_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
+  inv_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
+  inv_stage1<PR, 0, lay_a, 3>(x, tws, gtw2, lane);
 }
 
 }  // namespace vlp
