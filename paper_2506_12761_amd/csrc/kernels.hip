@@ -246,8 +246,9 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
     const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
     if (ab == 0) continue;  // the same decision in both wavefronts: abar is shared
-    // 64-bit accumulators of the two output polynomials mod P: canonical
-    // residues keep six products below P * 2^32 (one reduction at the end).
+    // 64-bit accumulators of the two output polynomials mod P: six products of
+    // transform values (< 4P) and key residues (< P) stay below 4P * 2^32, so
+    // one reduction at the end gives [0, 4P) and a conditional subtract [0, 2P).
     uint64_t m0[16], m1[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;
@@ -279,15 +280,16 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
           b1[r] = k0[2 * RING_N + r * 64 + lane];
         }
         const int shift = 32 - BG_BIT * (lev + 1);
+        // Balanced digit d in [-64, 63] as d + P in [P - 64, P + 63] (< 2P: the
+        // first stage takes inputs below 2P).
         uint32_t x[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = res_of((int32_t)((D[r] >> shift) & 127u) - 64, P);
+        for (int r = 0; r < 16; ++r) x[r] = ((D[r] >> shift) & 127u) + (P - 64);
         ntt_fwd1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const uint32_t d = csub(csub(x[r], 2 * P), P);  // [0, P)
-          m0[r] += (uint64_t)d * b0[r];
-          m1[r] += (uint64_t)d * b1[r];
+          m0[r] += (uint64_t)x[r] * b0[r];
+          m1[r] += (uint64_t)x[r] * b1[r];
         }
       }
     }
@@ -297,12 +299,12 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     constexpr int KEEP = PR;
     uint32_t keep[16], x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = redc(KEEP ? m1[r] : m0[r], P, PINV);
+    for (int r = 0; r < 16; ++r) x[r] = csub(redc(KEEP ? m1[r] : m0[r], P, PINV), 2 * P);
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       keep[r] = csub(x[r], P);
-      x[r] = redc(KEEP ? m0[r] : m1[r], P, PINV);
+      x[r] = csub(redc(KEEP ? m0[r] : m1[r], P, PINV), 2 * P);
     }
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
     wave_lds_sync();  // the transform's last reads of buf are done

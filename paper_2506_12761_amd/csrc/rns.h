@@ -58,12 +58,21 @@ __device__ __forceinline__ uint32_t shoup(uint32_t y, uint32_t w, uint32_t wp, u
 // x - m if x >= m, else x (for x < 2m): one subtract and one unsigned min.
 __device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t m) { return min(x, x - m); }
 
-// Montgomery reduction: T * 2^-32 mod p in [0, p), for T < p * 2^32.
+// Montgomery reduction: T * 2^-32 mod p in [0, p) for T < p * 2^32, and in
+// [0, 4p) for T < 4p * 2^32 (t is then in (-p, 4p) and 5p < 2^32).
 __device__ __forceinline__ uint32_t redc(uint64_t T, uint32_t p, uint32_t pinv) {
   const uint32_t m = (uint32_t)T * pinv;
   const uint32_t t = (uint32_t)(T >> 32) - __umulhi(m, p);  // exact: low words cancel
   return min(t, t + p);                                      // t < 0 wraps high; t + p is then in [0, p)
 }
+
+// Six products of a lazy transform value (< 4p) and a canonical key residue
+// (< p) sum below 24 p^2 < 2^64, whose high word stays below 4p: the
+// accumulators need no reduction of the transform output.
+static_assert((unsigned __int128)24 * P1 * P1 < ((unsigned __int128)1 << 64) &&
+                  (unsigned __int128)24 * P1 * P1 < ((unsigned __int128)4 * P1 << 32) &&
+                  (unsigned __int128)24 * P2 * P2 < ((unsigned __int128)4 * P2 << 32),
+              "accumulator range");
 
 // Low 32 bits of the centred lift of (x1 mod P1, x2 mod P2), canonical inputs.
 __device__ __forceinline__ uint32_t crt_lift_u32(uint32_t x1, uint32_t x2) {

@@ -65,7 +65,7 @@ __device__ __forceinline__ void wave_transpose(Poly2& v, uint2* buf, int lane) {
 }
 
 // Cooley-Tukey: (x, y) -> (x + w y, x - w y); in and out in [0, 4P).  With
-// CANON the input x is known to be < 2P already (first stage: canonical digits).
+// CANON the input x is known to be < 2P already (first stage: digit residues).
 template <bool CANON = false>
 __device__ __forceinline__ void bfly_ct(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp, uint32_t p) {
   const uint32_t u = CANON ? x : csub(x, 2 * p);
