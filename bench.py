@@ -203,6 +203,19 @@ def server_enc_bench(args):
         e1.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
         res[form] = {"ms_per_call": ms, "ciphertexts_per_s": count / (ms * 1e-3)}
+    # A plain device-to-device copy of the same public key, the practical ceiling.
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(ctx.stream):
+        out_loc.copy_(pk_loc)
+        out_pay.copy_(pk_pay)
+        e0.record(ctx.stream)
+        for _ in range(args.steps):
+            out_loc.copy_(pk_loc)
+            out_pay.copy_(pk_pay)
+        e1.record(ctx.stream)
+    e1.synchronize()
+    copy_ms = e0.elapsed_time(e1) / args.steps
+    res["device_copy"] = {"ms_per_call": copy_ms, "GB_per_s": count * 631 * 4 * 2 / (copy_ms * 1e-3) / 1e9}
     alg = count * 631 * 4 * 2 + M * 8 + M * lS  # words read + written, values, payload bytes
     gbs = alg / (res["copy"]["ms_per_call"] * 1e-3) / 1e9
     print(json.dumps({

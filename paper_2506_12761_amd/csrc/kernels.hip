@@ -492,16 +492,20 @@ __device__ __forceinline__ uint32_t enc_word(const int64_t* vals, const uint8_t*
 }
 
 // Out of place: four consecutive words per thread (16-byte accesses; pk and
-// out 16-byte aligned), the last words % 4 words by the first threads.
+// out 16-byte aligned), the last words % 4 words by the first threads.  IDX is
+// the index type: 32-bit when the array has fewer than 2^32 words (cheaper
+// division by 631), else 64-bit.  The output is written with non-temporal
+// stores: it is not read again by this pass.
+template <typename IDX>
 __global__ void server_enc_copy_kernel(const uint4* __restrict__ pk, uint4* __restrict__ out, size_t count,
                                        const int64_t* __restrict__ vals, const uint8_t* __restrict__ bytes,
                                        uint32_t l) {
-  const size_t words = count * CT_n, quads = words / 4;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
+  const IDX words = (IDX)(count * CT_n), quads = words / 4;
+  const IDX stride = (IDX)gridDim.x * blockDim.x;
+  for (IDX q = (IDX)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
     uint4 w = pk[q];
-    const size_t w0 = 4 * q;
-    const size_t t = w0 / CT_n;
+    const IDX w0 = 4 * q;
+    const IDX t = w0 / CT_n;
     const uint32_t r = (uint32_t)(w0 - t * CT_n);  // word index of w.x inside ciphertext t
     // The body word (CT_n - 1) is one of the four iff r >= CT_n - 4.
     if (r >= CT_n - 4) {
@@ -513,12 +517,15 @@ __global__ void server_enc_copy_kernel(const uint4* __restrict__ pk, uint4* __re
         default: w.w += e; break;
       }
     }
-    out[q] = w;
+    __builtin_nontemporal_store(w.x, &out[q].x);
+    __builtin_nontemporal_store(w.y, &out[q].y);
+    __builtin_nontemporal_store(w.z, &out[q].z);
+    __builtin_nontemporal_store(w.w, &out[q].w);
   }
-  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const IDX tid = (IDX)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid < words - 4 * quads) {
-    const size_t wi = 4 * quads + tid;
-    const size_t t = wi / CT_n;
+    const IDX wi = 4 * quads + tid;
+    const IDX t = wi / CT_n;
     uint32_t v = reinterpret_cast<const uint32_t*>(pk)[wi];
     if (wi - t * CT_n == CT_n - 1) v += enc_word(vals, bytes, l, t);
     reinterpret_cast<uint32_t*>(out)[wi] = v;
@@ -639,8 +646,12 @@ int launch_server_enc(const uint32_t* pk, uint32_t* out, size_t count, const int
     // in flight, grid-stride beyond that.
     const size_t quads = words / 4;
     const size_t blocks = std::max<size_t>(1, std::min<size_t>((quads + 255) / 256, 4096));
-    hipLaunchKernelGGL(server_enc_copy_kernel, dim3((uint32_t)blocks), dim3(256), 0, S(stream),
-                       reinterpret_cast<const uint4*>(pk), reinterpret_cast<uint4*>(out), count, vals, bytes, l);
+    if (words < (1ull << 32))
+      hipLaunchKernelGGL(server_enc_copy_kernel<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, S(stream),
+                         reinterpret_cast<const uint4*>(pk), reinterpret_cast<uint4*>(out), count, vals, bytes, l);
+    else
+      hipLaunchKernelGGL(server_enc_copy_kernel<uint64_t>, dim3((uint32_t)blocks), dim3(256), 0, S(stream),
+                         reinterpret_cast<const uint4*>(pk), reinterpret_cast<uint4*>(out), count, vals, bytes, l);
   } else {
     const size_t blocks = std::min<size_t>((words + 255) / 256, 8192);
     hipLaunchKernelGGL(server_enc_word_kernel, dim3((uint32_t)blocks), dim3(256), 0, S(stream), pk, out, count, vals,
