@@ -11,7 +11,8 @@ The circuits follow the paper's algorithms in their order of gates:
   IntV         Alg. 4; CoV Alg. 8; IdM = HomEqOPT on identifier bits (Sec. 4.2);
   selection    Alg. 9 (HomBitwiseAND);
   aggregation  Alg. 10 (HomSum, XOR chain from a trivial 0) and its pairwise
-               XOR-tree form of Section 6.1, part (5);
+               XOR-tree form of Section 6.1, part (5); and, beyond the paper,
+               a k-ary tree of k-input XORs (one bootstrap per k inputs);
   query        Alg. 3 (validate, zero out, aggregate).
 Bits are least-significant first; bit l-1 is the two's-complement sign
 (Appendix A, proof of Theorem 1).
@@ -30,6 +31,8 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 
 from . import oracle as O
+
+XORK = "xork"  # graph node kind of the k-input XOR
 
 
 # ----------------------------------------------------------------------------
@@ -114,6 +117,24 @@ def homsum_tree(B, S):
     return S[0]
 
 
+def homsum_ktree(B, S, k: int):
+    """Aggregation by k-input XORs: the records' selected bits are taken in
+    consecutive groups of k, each group XORed with one bootstrap (a group of
+    one passes through), and the group results reduced the same way until one
+    remains.  k = 2 is a pairwise tree (grouping 0-1, 2-3, ... per round)."""
+    cur = [list(x) for x in S]
+    while len(cur) > 1:
+        nxt = []
+        for g in range(0, len(cur), k):
+            grp = cur[g:g + k]
+            if len(grp) == 1:
+                nxt.append(grp[0])
+            else:
+                nxt.append([B.xork([row[j] for row in grp]) for j in range(len(grp[0]))])
+        cur = nxt
+    return cur[0]
+
+
 def homsum_chain(B, S):
     """HomSum (Alg. 10): R = trivial zeros; R[j] = XOR(R[j], S_i[j]) for every record."""
     R = [B.trivial(0) for _ in S[0]]
@@ -122,11 +143,12 @@ def homsum_chain(B, S):
     return R
 
 
-def query(B, mode: str, q, db_loc, db_pay, l: int, optimized: bool = True):
+def query(B, mode: str, q, db_loc, db_pay, l: int, optimized: bool = True, agg_k: int = 0):
     """VeLoPIR (Alg. 3): returns (v per record, R or None).
 
     mode: "intv" (db_loc[i] = [(left, right)] per coordinate), "cov"
-    (db_loc[i] = [bits] per coordinate) or "idm" (db_loc[i] = id bits, q = id bits)."""
+    (db_loc[i] = [bits] per coordinate) or "idm" (db_loc[i] = id bits, q = id bits).
+    agg_k >= 2 aggregates with k-input XORs instead of Alg. 10 / the pairwise tree."""
     eq = eq_opt if optimized else eq_chain
     vs = []
     for loc in db_loc:
@@ -141,7 +163,10 @@ def query(B, mode: str, q, db_loc, db_pay, l: int, optimized: bool = True):
     if db_pay is None:
         return vs, None
     sel = [select(B, v, S) for v, S in zip(vs, db_pay)]
-    R = homsum_tree(B, sel) if optimized else homsum_chain(B, sel)
+    if agg_k >= 2:
+        R = homsum_ktree(B, sel, agg_k)
+    else:
+        R = homsum_tree(B, sel) if optimized else homsum_chain(B, sel)
     return vs, R
 
 
@@ -165,6 +190,12 @@ class PlainBuilder:
 
     def mux(self, s, x, y):
         return np.where(s, x, y)
+
+    def xork(self, args):
+        r = args[0]
+        for a in args[1:]:
+            r = np.logical_xor(r, a)
+        return r
 
 
 class GraphBuilder:
@@ -207,6 +238,9 @@ class GraphBuilder:
     def mux(self, s, x, y):
         return self._gate(O.MUX, s, x, y)
 
+    def xork(self, args):
+        return self._gate(XORK, *args)
+
     def counts(self):
         """(gates, blind rotations) of the recorded graph."""
         g = br = 0
@@ -236,6 +270,8 @@ class GraphBuilder:
         def run(i):
             nd = self.nodes[i]
             args = [vals[a] for a in nd[1:]]
+            if nd[0] == XORK:
+                return O.xor_k(keys, args)
             while len(args) < 3:
                 args.append(None)
             return O.gate(keys, nd[0], *args)

@@ -250,6 +250,23 @@ def gate(keys: Keys, op, a, b=None, c=None) -> np.ndarray:
     return out
 
 
+def xor_k(keys: Keys, cts) -> np.ndarray:
+    """XOR of k >= 2 ciphertexts with one bootstrap: the k-input form of the
+    XOR gate's pre-combination, (0, (k-1)/4) + 2 * (c_1 + ... + c_k), whose
+    phase is -1/4 for an even number of ones and +1/4 for an odd number; then
+    BlindRotate with test value 1/8, SampleExtract and KeySwitch.  k = 2 is
+    the XOR gate (0, 1/4) + 2(a + b).  Noise: 4k times an input's variance."""
+    cts = [_u32(c) for c in cts]
+    k = len(cts)
+    if k < 2:
+        raise ValueError("xor_k needs at least two inputs")
+    acc = np.zeros(n + 1, np.uint64)
+    for c in cts:
+        acc += 2 * c.astype(np.uint64)
+    acc[n] += (k - 1) * (1 << 30)
+    return bootstrap(keys, (acc & np.uint64(0xFFFFFFFF)).astype(np.uint32), MU)
+
+
 def modswitch_arr(x) -> np.ndarray:
     x = _u32(x)
     out = np.zeros_like(x)

@@ -97,7 +97,7 @@ def record_slice(P: dict, enc: dict, idx) -> tuple[dict, dict]:
     return Q, e
 
 
-def graph_for(mode: str, M: int, l: int, lS: int, d: int, optimized: bool = True):
+def graph_for(mode: str, M: int, l: int, lS: int, d: int, optimized: bool = True, agg_k: int = 0):
     """Circuit graph of the whole query with input keys naming array positions."""
     G = C.GraphBuilder()
     if mode == "idm":
@@ -111,13 +111,13 @@ def graph_for(mode: str, M: int, l: int, lS: int, d: int, optimized: bool = True
         q = [[G.input(("query", (k, i))) for i in range(l)] for k in range(d)]
         db = [[[G.input(("db_loc", (r, k, i))) for i in range(l)] for k in range(d)] for r in range(M)]
     pay = [[G.input(("db_pay", (r, j))) for j in range(lS)] for r in range(M)] if lS else None
-    vs, R = C.query(G, mode, q, db, pay, l, optimized=optimized)
+    vs, R = C.query(G, mode, q, db, pay, l, optimized=optimized, agg_k=agg_k)
     return G, vs, R
 
 
-def oracle_outputs(keys: O.Keys, P: dict, enc: dict, optimized: bool = True, threads=None):
+def oracle_outputs(keys: O.Keys, P: dict, enc: dict, optimized: bool = True, threads=None, agg_k: int = 0):
     """(v [M][631], R [lS][631]) computed by the oracle."""
-    G, vs, R = graph_for(P["mode"], P["M"], P["l"], P["lS"], P["d"], optimized)
+    G, vs, R = graph_for(P["mode"], P["M"], P["l"], P["lS"], P["d"], optimized, agg_k)
     inputs = {}
     for nd in G.nodes:
         if nd[0] == "in":
