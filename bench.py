@@ -131,8 +131,9 @@ TABLE3 = [("covid-kor", "intv", 9, 16, 9), ("covid-kor", "idm", 9, 16, 9), ("cov
 
 def table3_bench(args):
     """One full query (Algorithm 3) per Table-3 shape, baseline circuits
-    (Alg. 7 AND chain, Alg. 10 XOR chain) and optimized circuits (Alg. 11/12,
-    XOR tree); synthetic uniform data of those shapes; latency per query."""
+    (Alg. 7 AND chain, Alg. 10 XOR chain), optimized circuits (Alg. 11/12,
+    XOR tree) and optimized circuits with 16-input XOR aggregation; synthetic
+    uniform data of those shapes; latency per query."""
     from paper_2506_12761_amd import synth, vlp
     ctx = vlp.Context(0)
     bk, ksk = synth.uniform_keys(0x5EED0006)
@@ -147,8 +148,8 @@ def table3_bench(args):
         pay = ctx.tensor(synth.uniform_ciphertexts(k, "p", (M, lS)))
         R, v = ctx.empty(lS, 631), ctx.empty(M, 631)
         rec = {"dataset": name, "mode": mode, "M": M, "l_I": l, "l_S": lS}
-        for opt in (False, True):
-            sh = vlp.make_shape(mode, M, l, lS, d, opt)
+        for opt, agg_k in ((False, 0), (True, 0), (True, 16)):
+            sh = vlp.make_shape(mode, M, l, lS, d, opt, agg_k)
             plan = vlp.vlp_plan_counts(sh)
             vlp.vlp_evaluate(ctx.ctx, ks, sh, q, loc, pay, R, v)  # build + warm
             ctx.sync()
@@ -157,9 +158,10 @@ def table3_bench(args):
                 vlp.vlp_evaluate(ctx.ctx, ks, sh, q, loc, pay, R, v)
             ctx.sync()
             dt = (time.perf_counter() - t0) / args.steps
-            rec["opt" if opt else "base"] = {"s": dt, "blind_rotations": plan["blind_rotations"],
-                                              "levels": plan["levels"]}
+            key = "base" if not opt else ("opt" if not agg_k else "opt_xor16")
+            rec[key] = {"s": dt, "blind_rotations": plan["blind_rotations"], "levels": plan["levels"]}
         rec["speedup_opt_vs_base"] = rec["base"]["s"] / rec["opt"]["s"]
+        rec["speedup_opt_xor16_vs_base"] = rec["base"]["s"] / rec["opt_xor16"]["s"]
         log(json.dumps(rec))
         rows.append(rec)
     print(json.dumps({"metric": "PIR query latency per Table-3 shape, baseline vs optimized circuits, 1 GPU",
@@ -308,6 +310,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the level sequence as a HIP graph "
                     "(disables per-launch timing)")
     ap.add_argument("--records", type=int, default=0, help="override the record count of every program")
+    ap.add_argument("--agg-k", type=int, default=0, help="aggregate with k-input XORs (2..16) where l_S > 0")
     ap.add_argument("--tuned", action="store_true", help="apply the cached autotuner result")
     ap.add_argument("--br-waves", type=int, default=0, help="waves per blind-rotation workgroup (1, 2, 4, 8)")
     ap.add_argument("--br-blocks", type=int, default=0, help="blind-rotation workgroups per CU the grid is sized for")
@@ -383,8 +386,8 @@ def main():
         d_R = ctx.empty(lS, 631) if lS else None
         d_v = ctx.empty(M, 631)
         keep.append((d_q, d_loc, d_pay, d_R, d_v))
-        progs.append(vlp.vlp_program_create(ctx.ctx, ks, vlp.make_shape(mode, M, l, lS, d), d_q, d_loc, d_pay,
-                                            d_R, d_v))
+        shape = vlp.make_shape(mode, M, l, lS, d, True, args.agg_k if lS else 0)
+        progs.append(vlp.vlp_program_create(ctx.ctx, ks, shape, d_q, d_loc, d_pay, d_R, d_v))
     counts = [vlp.vlp_program_counts(ctx.ctx, pr) for pr in progs]
     br_step = sum(c["blind_rotations"] for c in counts)
     ks_step = sum(c["key_switches"] for c in counts)
@@ -489,7 +492,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic (seeded uniform keys and ciphertexts)",
-        "config": {"workload": wl["label"], "programs": specs,
+        "config": {"workload": wl["label"], "programs": specs, "agg_k": args.agg_k,
                    "blind_rotations_per_step": br_step, "key_switches_per_step": ks_step,
                    "levels": levels, "graph": bool(args.graph), "launch": launch},
         "gates_per_s": gates_step * args.steps / elapsed,

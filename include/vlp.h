@@ -82,11 +82,19 @@ typedef struct {
  * d coordinates (1 or 2 for IntV and CoV; ignored for IdM).
  * optimized = 1 uses the OPT circuits (Alg. 11 comparators, Alg. 12 equality
  * tree, pairwise XOR aggregation); 0 uses Alg. 7's AND chain and Alg. 10's
- * XOR chain from a trivial zero. */
+ * XOR chain from a trivial zero.
+ * agg_k = 0 aggregates as `optimized` says; 2 <= agg_k <= 16 replaces the
+ * aggregation (HomSum, Alg. 10) by a tree of k-input XORs, each one bootstrap
+ * of (0, (k-1)/4) + 2 * (sum of its k inputs): records' selected bits in
+ * consecutive groups of k, a group of one passed through, repeated on the
+ * group results.  Not in the paper; k <= 16 keeps the summed input noise
+ * (4k times a gate output's) beyond 8 standard deviations of the 1/4
+ * decision distance. */
 typedef struct {
     vlp_mode mode;
     uint32_t M, l_I, l_S, d;
     uint32_t optimized;
+    uint32_t agg_k;
 } vlp_shape;
 
 typedef struct vlp_ctx vlp_ctx;

@@ -27,8 +27,9 @@ constexpr size_t BK_NTT_WORDS = (size_t)LWE_n * BK_ROW_WORDS;
 // Re-laid key-switching key: [1024][8][3 digits 1..3][640] words.
 constexpr size_t KSK_WORDS = (size_t)RING_N * KS_T * 3 * KS_ROW;       // u32 words
 
-// One blind rotation: input = (0, cst) + ca * a + cb * b, output the
-// sample-extracted LWE_N ciphertext of BlindRotate(input, mu).
+// One blind rotation: input = (0, cst) + ca * a + cb * b + cm * (more[0] +
+// ... + more[n_more - 1]), output the sample-extracted LWE_N ciphertext of
+// BlindRotate(input, mu).
 struct BrItem {
   const uint32_t* a;
   const uint32_t* b;    // may be null (then cb is ignored)
@@ -36,6 +37,9 @@ struct BrItem {
   const uint32_t* bk;   // transformed bootstrapping key
   int32_t ca, cb;
   uint32_t cst, mu;
+  const uint32_t* const* more;  // n_more further operands (k-input XOR), or null
+  uint32_t n_more;
+  int32_t cm;
 };
 
 // One key switch: input = u1 + u2 + (0, cst) in dimension N, output LWE_n.

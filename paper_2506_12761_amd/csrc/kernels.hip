@@ -98,6 +98,7 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
     for (int w = lane; w < CT_n; w += 64) {
       uint32_t x = (uint32_t)I.ca * in_a[w];
       if (I.b) x += (uint32_t)I.cb * in_b[w];
+      for (uint32_t t = 0; t < I.n_more; ++t) x += (uint32_t)I.cm * ((const g_u32*)I.more[t])[w];
       if (w == LWE_n) x += I.cst;
       abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
     }
@@ -351,6 +352,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void b
     for (int w = threadIdx.x; w < CT_n; w += 128) {
       uint32_t x = (uint32_t)I.ca * in_a[w];
       if (I.b) x += (uint32_t)I.cb * in_b[w];
+      for (uint32_t t = 0; t < I.n_more; ++t) x += (uint32_t)I.cm * ((const g_u32*)I.more[t])[w];
       if (w == LWE_n) x += I.cst;
       s_abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
     }
@@ -461,6 +463,9 @@ __global__ void make_br_items_kernel(BrItem* items, uint32_t count, const uint32
   it.cb = cb;
   it.cst = cst;
   it.mu = mu;
+  it.more = nullptr;
+  it.n_more = 0;
+  it.cm = 0;
   items[t] = it;
 }
 

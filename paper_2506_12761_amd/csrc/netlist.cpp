@@ -6,7 +6,8 @@
 //                or Alg. 7 (AND chain from a trivial 1)
 //   IntV Alg. 4, CoV Alg. 8, IdM (HomEQ on identifier bits, Section 4.2)
 //   zero-out     Alg. 9;  aggregation: pairwise XOR tree (Section 6.1 (5)) or
-//                Alg. 10's XOR chain from a trivial 0.
+//                Alg. 10's XOR chain from a trivial 0, or (agg_k, beyond the
+//                paper) a tree of k-input XORs.
 // Bits are least-significant first; bit l-1 is the sign bit.
 #include "netlist.h"
 
@@ -61,6 +62,32 @@ struct Builder {
     nl.levels = std::max(nl.levels, g.level);
     return Operand::gate((uint32_t)nl.gates.size() - 1);
   }
+  // XOR of ops (size >= 1) with one bootstrap: (0, (k-1)/4) + 2 * sum.
+  Operand XORK(const std::vector<Operand>& ops) {
+    if (ops.size() == 1) return ops[0];
+    bool all_const = true;
+    int parity = 0;
+    uint32_t lvl = 0;
+    for (const Operand& o : ops) {
+      all_const = all_const && o.is_const();
+      parity ^= o.is_const() ? (int)o.index : 0;
+      lvl = std::max(lvl, level_of(o));
+    }
+    if (all_const) return Operand::cst(parity);
+    Gate g;
+    g.op = OP_XORK;
+    g.a = ops[0];
+    g.b = ops[1];
+    g.c = Operand();
+    g.level = 1 + lvl;
+    g.out_slot = -1;
+    g.xk_first = (uint32_t)nl.xk_ops.size();
+    g.xk_count = (uint32_t)ops.size() - 2;
+    for (size_t t = 2; t < ops.size(); ++t) nl.xk_ops.push_back(ops[t]);
+    nl.gates.push_back(g);
+    nl.levels = std::max(nl.levels, g.level);
+    return Operand::gate((uint32_t)nl.gates.size() - 1);
+  }
   Operand AND(Operand a, Operand b) { return gate(VLP_AND, a, b); }
   Operand XOR(Operand a, Operand b) { return gate(VLP_XOR, a, b); }
   Operand XNOR(Operand a, Operand b) { return gate(VLP_XNOR, a, b); }
@@ -107,6 +134,7 @@ bool shape_valid(const vlp_shape& sh, const char** why) {
   if (sh.mode == VLP_INTV && l < 2) { *why = "IntV needs l_I >= 2"; return false; }
   if (lS > 1024) { *why = "l_S must be <= 1024"; return false; }
   if (sh.mode != VLP_IDM && (d < 1 || d > 2)) { *why = "d must be 1 or 2"; return false; }
+  if (sh.agg_k == 1 || sh.agg_k > AGG_K_MAX) { *why = "agg_k must be 0 or in [2, 16]"; return false; }
   return true;
 }
 
@@ -154,7 +182,30 @@ bool build_netlist(const vlp_shape& sh, Netlist& nl, const char** why) {
   std::vector<std::vector<Operand>> S(M, std::vector<Operand>(lS));
   for (uint32_t i = 0; i < M; ++i)
     for (uint32_t j = 0; j < lS; ++j) S[i][j] = B.AND(nl.v_of_record[i], Operand::pay(i * lS + j));
-  if (opt) {
+  if (sh.agg_k >= 2) {
+    // Consecutive groups of k (a group of one passes through), repeated on the group results.
+    const uint32_t K = sh.agg_k;
+    std::vector<std::vector<Operand>> cur = S;
+    while (cur.size() > 1) {
+      std::vector<std::vector<Operand>> nxt;
+      for (size_t g0 = 0; g0 < cur.size(); g0 += K) {
+        const size_t gn = std::min<size_t>(K, cur.size() - g0);
+        if (gn == 1) {
+          nxt.push_back(cur[g0]);
+          continue;
+        }
+        std::vector<Operand> row(lS);
+        for (uint32_t j = 0; j < lS; ++j) {
+          std::vector<Operand> ops(gn);
+          for (size_t t = 0; t < gn; ++t) ops[t] = cur[g0 + t][j];
+          row[j] = B.XORK(ops);
+        }
+        nxt.push_back(row);
+      }
+      cur.swap(nxt);
+    }
+    nl.result = cur[0];
+  } else if (opt) {
     for (uint32_t k = 1; k < M; k *= 2)
       for (uint32_t i = 0; i < M; i += 2 * k)
         if (i + k < M)

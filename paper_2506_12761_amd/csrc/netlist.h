@@ -22,11 +22,17 @@ struct Operand {
   bool is_const() const { return src == Src::Const; }
 };
 
+// Internal op of the k-input XOR (aggregation with agg_k): operands a, b and
+// Netlist::xk_ops[xk_first .. xk_first + xk_count).
+constexpr uint8_t OP_XORK = 7;
+constexpr uint32_t AGG_K_MAX = 16;
+
 struct Gate {
-  uint8_t op;        // vlp_gate_op (AND, XOR, XNOR, MUX, ...)
+  uint8_t op;        // vlp_gate_op (AND, XOR, XNOR, MUX, ...) or OP_XORK
   Operand a, b, c;   // MUX(a = select, b = if 1, c = if 0)
   uint32_t level;    // 1 + max level of the gate operands (inputs are level 0)
   int32_t out_slot;  // >= 0: written to user output slot (v_out / R), else internal
+  uint32_t xk_first = 0, xk_count = 0;  // OP_XORK: operands beyond a and b
 };
 
 // Output slots: validation bit of record i -> slot i; aggregated bit j -> slot M + j.
@@ -36,6 +42,7 @@ struct Netlist {
   uint32_t M = 0, l_S = 0;
   std::vector<Operand> v_of_record;  // M entries
   std::vector<Operand> result;       // l_S entries (R), may be gates or inputs
+  std::vector<Operand> xk_ops;       // extra operands of OP_XORK gates
   uint64_t blind_rotations() const;
   uint64_t key_switches() const;
 };

@@ -61,6 +61,7 @@ struct vlp_program {
   KsItem* ks_items = nullptr;
   uint32_t* gate_buf = nullptr;   // internal gate outputs [n_internal][631]
   uint32_t* ext_buf = nullptr;    // LWE_N slots [max BR per level][1025]
+  const uint32_t** more_buf = nullptr;  // operand lists of k-input XOR items
   size_t bytes = 0;
   uint32_t max_br_level = 0;
   hipGraph_t graph = nullptr;
@@ -486,6 +487,7 @@ static void program_free(vlp_program* prog) {
   dev_free(ctx, prog->ks_items, 0);
   dev_free(ctx, prog->gate_buf, 0);
   dev_free(ctx, prog->ext_buf, 0);
+  dev_free(ctx, prog->more_buf, 0);
   ctx->used -= prog->bytes;
   prog->ks->users--;
   ctx->live_programs--;
@@ -593,9 +595,18 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
     max_br = std::max(max_br, nbr);
   }
   const uint64_t n_br = nl.blind_rotations(), n_ks = nl.key_switches();
+  // Operand-list entries of the k-input XORs: the non-trivial operands past the first two.
+  size_t n_more = 0;
+  for (const Gate& G : nl.gates) {
+    if (G.op != OP_XORK) continue;
+    size_t live = (G.a.is_const() ? 0 : 1) + (G.b.is_const() ? 0 : 1);
+    for (uint32_t t = 0; t < G.xk_count; ++t) live += nl.xk_ops[G.xk_first + t].is_const() ? 0 : 1;
+    n_more += live > 2 ? live - 2 : 0;
+  }
   const size_t b_items = n_br * sizeof(BrItem), k_items = n_ks * sizeof(KsItem);
   const size_t b_gate = (size_t)n_internal * CT_n * 4, b_ext = (size_t)max_br * CT_N * 4;
-  const size_t total = b_items + k_items + b_gate + b_ext;
+  const size_t b_more = n_more * sizeof(const uint32_t*);
+  const size_t total = b_items + k_items + b_gate + b_ext + b_more;
   if (ctx->used + total > ctx->budget)
     return fail(ctx, VLP_EBUDGET, "program needs %zu bytes; %zu of %zu in use", total, ctx->used, ctx->budget);
 
@@ -617,11 +628,13 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   if (e == hipSuccess && k_items) e = hipMalloc((void**)&prog->ks_items, k_items);
   if (e == hipSuccess && b_gate) e = hipMalloc((void**)&prog->gate_buf, b_gate);
   if (e == hipSuccess && b_ext) e = hipMalloc((void**)&prog->ext_buf, b_ext);
+  if (e == hipSuccess && b_more) e = hipMalloc((void**)&prog->more_buf, b_more);
   if (e != hipSuccess) {
     (void)hipFree(prog->br_items);
     (void)hipFree(prog->ks_items);
     (void)hipFree(prog->gate_buf);
     (void)hipFree(prog->ext_buf);
+    (void)hipFree(prog->more_buf);
     delete prog;
     return fail(ctx, VLP_EHIP, "program allocation: %s", hipGetErrorString(e));
   }
@@ -674,6 +687,35 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
     it.bk = ks->bk_ntt;
     return it;
   };
+  std::vector<const uint32_t*> hm;  // operand lists of k-input XOR items
+  hm.reserve(n_more);
+  // A k-input XOR unit: (0, (k-1)/4) + 2 * (sum of the operands), trivial ones folded.
+  auto xork_unit = [&](const Gate& G, uint32_t* out) {
+    std::vector<Operand> ops{G.a, G.b};
+    for (uint32_t t = 0; t < G.xk_count; ++t) ops.push_back(nl.xk_ops[G.xk_first + t]);
+    uint32_t cst = (uint32_t)(ops.size() - 1) << 30;
+    std::vector<const uint32_t*> live;
+    for (const Operand& o : ops) {
+      if (o.is_const()) cst += 2u * encode_bit(o.index);
+      else live.push_back(ptr(o));
+    }
+    BrItem it{};
+    it.a = live[0];
+    it.ca = 2;
+    it.b = live.size() > 1 ? live[1] : nullptr;
+    it.cb = live.size() > 1 ? 2 : 0;
+    if (live.size() > 2) {
+      it.more = prog->more_buf + hm.size();
+      it.n_more = (uint32_t)(live.size() - 2);
+      it.cm = 2;
+      for (size_t t = 2; t < live.size(); ++t) hm.push_back(live[t]);
+    }
+    it.cst = cst;
+    it.mu = MU;
+    it.out = out;
+    it.bk = ks->bk_ntt;
+    return it;
+  };
   std::vector<BrItem> hb;
   std::vector<KsItem> hk;
   hb.reserve(n_br);
@@ -695,6 +737,12 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
         k.u1 = u1;
         k.u2 = u2;
         k.cst = MU;
+      } else if (G.op == OP_XORK) {
+        uint32_t* u1 = prog->ext_buf + (size_t)e_slot++ * CT_N;
+        hb.push_back(xork_unit(G, u1));
+        k.u1 = u1;
+        k.u2 = nullptr;
+        k.cst = 0;
       } else {
         int32_t ca, cb;
         uint32_t cst;
@@ -713,6 +761,7 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   }
   if (b_items) e = hipMemcpy(prog->br_items, hb.data(), b_items, hipMemcpyHostToDevice);
   if (e == hipSuccess && k_items) e = hipMemcpy(prog->ks_items, hk.data(), k_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess && b_more) e = hipMemcpy(prog->more_buf, hm.data(), b_more, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     program_free(prog);
     return fail(ctx, VLP_EHIP, "program upload: %s", hipGetErrorString(e));

@@ -48,7 +48,8 @@ class vlp_params(ctypes.Structure):
 
 class vlp_shape(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("M", ctypes.c_uint32), ("l_I", ctypes.c_uint32),
-                ("l_S", ctypes.c_uint32), ("d", ctypes.c_uint32), ("optimized", ctypes.c_uint32)]
+                ("l_S", ctypes.c_uint32), ("d", ctypes.c_uint32), ("optimized", ctypes.c_uint32),
+                ("agg_k", ctypes.c_uint32)]
 
 
 class vlp_kernel_stats(ctypes.Structure):
@@ -185,10 +186,10 @@ def vlp_gate(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B: int) -> None:
     _check(ctx, lib().vlp_gate(ctx, ks, op, _ptr(a_dev), _ptr(b_dev), _ptr(c_dev), _ptr(out_dev), B))
 
 
-def make_shape(mode, M, l_I, l_S=0, d=2, optimized=True) -> vlp_shape:
+def make_shape(mode, M, l_I, l_S=0, d=2, optimized=True, agg_k=0) -> vlp_shape:
     if isinstance(mode, str):
         mode = MODES[mode]
-    return vlp_shape(mode, M, l_I, l_S, d, 1 if optimized else 0)
+    return vlp_shape(mode, M, l_I, l_S, d, 1 if optimized else 0, agg_k)
 
 
 def vlp_evaluate(ctx, ks, shape: vlp_shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev) -> None:

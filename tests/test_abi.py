@@ -44,7 +44,7 @@ def test_bad_params_rejected_without_device():
     assert e.value.status == vlp.VLP_EPARAM
 
 
-def _oracle_counts(mode, M, l, lS, d, opt=True):
+def _oracle_counts(mode, M, l, lS, d, opt=True, agg_k=0):
     G = C.GraphBuilder()
     if mode == "intv":
         q = [[G.input(("q", k, i)) for i in range(l)] for k in range(d)]
@@ -57,7 +57,7 @@ def _oracle_counts(mode, M, l, lS, d, opt=True):
         q = [G.input(("q", i)) for i in range(l)]
         db = [[G.input(("id", r, i)) for i in range(l)] for r in range(M)]
     pay = [[G.input(("S", r, j)) for j in range(lS)] for r in range(M)] if lS else None
-    C.query(G, mode, q, db, pay, l, optimized=opt)
+    C.query(G, mode, q, db, pay, l, optimized=opt, agg_k=agg_k)
     g, br = G.counts()
     return g, br, G.depth()
 
@@ -73,6 +73,22 @@ def test_plan_counts_match_oracle_graph(case):
         g, br, depth = _oracle_counts(mode, M, l, lS, d, opt)
         assert (c["gates"], c["blind_rotations"], c["levels"]) == (g, br, depth), (case, opt)
         assert c["key_switches"] == g
+
+
+@pytest.mark.parametrize("case", [("idm", 9, 16, 9, 1), ("idm", 58, 16, 22, 1), ("intv", 5, 6, 4, 2),
+                                  ("cov", 17, 5, 3, 2), ("idm", 1, 8, 4, 1)])
+@pytest.mark.parametrize("k", [2, 3, 16])
+def test_plan_counts_k_ary_aggregation(case, k):
+    mode, M, l, lS, d = case
+    c = vlp.vlp_plan_counts(vlp.make_shape(mode, M, l, lS, d, True, agg_k=k))
+    g, br, depth = _oracle_counts(mode, M, l, lS, d, True, agg_k=k)
+    assert (c["gates"], c["blind_rotations"], c["levels"]) == (g, br, depth), (case, k)
+
+
+def test_plan_rejects_bad_agg_k():
+    for k in (1, 17, 100):
+        with pytest.raises(vlp.VlpError):
+            vlp.vlp_plan_counts(vlp.make_shape("idm", 4, 8, 2, 1, True, agg_k=k))
 
 
 def test_plan_counts_of_the_workloads():

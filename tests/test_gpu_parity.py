@@ -85,7 +85,7 @@ def test_gate_parity(gpu, oracle_keys, op):
         assert int(O.decrypt(oracle_keys, got[k])) == truth(*[int(bits[i, k]) for i in range(3)])
 
 
-def _run_eval(gpu, keys, mode, M, l, lS, d, seed, optimized=True, use_graph_twice=False):
+def _run_eval(gpu, keys, mode, M, l, lS, d, seed, optimized=True, use_graph_twice=False, agg_k=0):
     vlp, ctx, ks = gpu
     P = W.plain_workload(mode, M, l, lS, d, seed)
     enc = W.encrypt_workload(keys, P, seed)
@@ -93,7 +93,7 @@ def _run_eval(gpu, keys, mode, M, l, lS, d, seed, optimized=True, use_graph_twic
     pay = ctx.tensor(enc["db_pay"]) if lS else None
     R = ctx.empty(lS, O.n + 1) if lS else None
     v = ctx.empty(M, O.n + 1)
-    shape = vlp.make_shape(mode, M, l, lS, d, optimized)
+    shape = vlp.make_shape(mode, M, l, lS, d, optimized, agg_k)
     vlp.vlp_evaluate(ctx.ctx, ks, shape, q, loc, pay, R, v)
     ctx.sync()
     res = [(ctx.to_host(v).copy(), ctx.to_host(R).copy() if lS else None)]
@@ -129,6 +129,21 @@ def test_evaluate_unoptimized_parity(gpu, oracle_keys):
     P, enc, res = _run_eval(gpu, oracle_keys, "cov", 3, 4, 2, 2, seed=77, optimized=False)
     v_want, R_want = W.oracle_outputs(oracle_keys, P, enc, optimized=False)
     assert np.array_equal(res[0][0], v_want) and np.array_equal(res[0][1], R_want)
+
+
+@pytest.mark.parametrize("mode,M,l,lS,d,k", [("idm", 7, 4, 3, 1, 3), ("idm", 18, 3, 2, 1, 16),
+                                              ("intv", 5, 5, 2, 2, 4), ("cov", 3, 4, 2, 1, 2)])
+def test_evaluate_k_ary_aggregation_parity(gpu, oracle_keys, mode, M, l, lS, d, k):
+    """Aggregation by k-input XORs (operand lists of up to 16 ciphertexts in
+    the blind rotation's pre-combination) equals the oracle word for word,
+    also on the replayed graph; 18 records at k = 16 leave a group of two."""
+    P, enc, res = _run_eval(gpu, oracle_keys, mode, M, l, lS, d, seed=1000 + M * k, use_graph_twice=True,
+                            agg_k=k)
+    v_want, R_want = W.oracle_outputs(oracle_keys, P, enc, agg_k=k)
+    for v_got, R_got in res:
+        assert np.array_equal(v_got, v_want)
+        assert np.array_equal(R_got, R_want)
+        assert np.array_equal(O.decrypt(oracle_keys, R_got), P["R"])
 
 
 def test_step_merges_programs(gpu, oracle_keys):
