@@ -47,7 +47,7 @@ PEAK_MODMUL = VALU_LANE_OPS / OPS_PER_MODMUL  # 2.4576e12 modmul/s
 # copy-calibrated), valid only for the kernel sources it was measured on
 # (their sha256 prefix) and the launch shape it was measured with.
 TRAFFIC_MEASURED = {"kernel_sha": "f1611892a4f28ae7", "bytes_per_launch": 1.65059e+09,
-                    "launch": {"br_prime_split": 1, "br_waves_per_block": 4, "br_blocks_per_cu": 4,
+                    "launch": {"br_waves_per_rotation": 2, "br_waves_per_block": 4, "br_blocks_per_cu": 4,
                                "ks_gates_per_block": 4}}
 KERNEL_SOURCES = ("kernels.hip", "wave_ntt.h", "rns.h", "vlp_api.cpp")
 
@@ -314,8 +314,8 @@ def main():
     ap.add_argument("--tuned", action="store_true", help="apply the cached autotuner result")
     ap.add_argument("--br-waves", type=int, default=0, help="waves per blind-rotation workgroup (1, 2, 4, 8)")
     ap.add_argument("--br-blocks", type=int, default=0, help="blind-rotation workgroups per CU the grid is sized for")
-    ap.add_argument("--br-split", type=int, default=-1, choices=(-1, 0, 1),
-                    help="1: two wavefronts per blind rotation, one per prime; 0: one wavefront")
+    ap.add_argument("--br-waves-per-rotation", type=int, default=-1, choices=(-1, 0, 1, 2, 4),
+                    help="wavefronts per blind rotation (0: automatic by launch size)")
     ap.add_argument("--serve", action="store_true", help="run the serving experiment instead")
     ap.add_argument("--table3", action="store_true", help="replay the paper's dataset shapes instead")
     ap.add_argument("--server-enc", action="store_true", help="time ServerEnc of a 65,536-record database instead")
@@ -368,12 +368,13 @@ def main():
     if args.tuned:
         from paper_2506_12761_amd import autotune
         log("cached tuning applied: %s" % autotune.load_cached(ctx, args.workload))
-    if args.br_waves or args.br_blocks or args.br_split >= 0:
+    if args.br_waves or args.br_blocks or args.br_waves_per_rotation >= 0:
         t = vlp.vlp_get_tuning(ctx.ctx)
         vlp.vlp_set_tuning(ctx.ctx, args.br_waves or t.br_waves_per_block, args.br_blocks or t.br_blocks_per_cu,
-                           t.ks_gates_per_block, args.br_split if args.br_split >= 0 else t.br_prime_split)
+                           t.ks_gates_per_block,
+                           args.br_waves_per_rotation if args.br_waves_per_rotation >= 0 else t.br_waves_per_rotation)
     t = vlp.vlp_get_tuning(ctx.ctx)
-    launch = {"br_prime_split": t.br_prime_split, "br_waves_per_block": t.br_waves_per_block,
+    launch = {"br_waves_per_rotation": t.br_waves_per_rotation, "br_waves_per_block": t.br_waves_per_block,
               "br_blocks_per_cu": t.br_blocks_per_cu, "ks_gates_per_block": t.ks_gates_per_block}
     progs, keep = [], []
     for k, p in enumerate(specs):
@@ -469,7 +470,8 @@ def main():
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MODMUL / 1e12,
                     "unit": "Tmodmul/s", "frac": achieved / PEAK_MODMUL, "traffic": traffic,
                     "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": alg_bytes,
-                    "kernel": "br2_kernel" if launch["br_prime_split"] else "br_kernel",
+                    "kernel": {0: "br2_kernel (br4_kernel for short rounds)", 1: "br_kernel", 2: "br2_kernel",
+                               4: "br4_kernel"}[launch["br_waves_per_rotation"]],
                     "launches": br["launches"], "avg_launch_ms": avg_ms,
                     "ks_kernel_ms_share": prof["ks"]["ms"] / max(1e-9, prof["ks"]["ms"] + br["ms"])}
 

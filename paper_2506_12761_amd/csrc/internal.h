@@ -63,6 +63,8 @@ int launch_server_enc(const uint32_t* pk, uint32_t* out, size_t count, const int
                       uint32_t l, void* stream);
 // Two wavefronts per rotation (one per prime), one rotation per workgroup.
 int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream);
+// Four wavefronts per rotation (prime x accumulator half), one rotation per workgroup.
+int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream);
 int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream);
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
                          uint32_t cst, uint32_t mu, uint32_t* out, const uint32_t* bk, void* stream);

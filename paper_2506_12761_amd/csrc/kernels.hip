@@ -383,6 +383,166 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void b
 }
 
 // ---------------------------------------------------------------------------
+// Blind rotation split by prime and by accumulator half: a workgroup of four
+// wavefronts per item; wave w = PR + 2H computes, modulo prime PR, the three
+// digit polynomials of accumulator polynomial H and its products with the key
+// rows for both outputs.  Per CMux each wavefront runs 3 forward and 1 inverse
+// transform (half the split form's), so one rotation takes about half as
+// long; three workgroup barriers per CMux:
+//   B1  partial sums: wave (PR, H) receives from (PR, 1-H) the partial of
+//       output H over the other three digits, adds it to its own and runs the
+//       inverse transform of output H modulo PR;
+//   B2  CRT: waves (0, H) and (1, H) swap half of their residues, each lifts
+//       8 of the 16 registers of output H and updates the accumulator;
+//   B3  the accumulator is complete for the next CMux.
+// ---------------------------------------------------------------------------
+template <int PR, int H>
+__device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const uint16_t* abar, uint32_t* buf,
+                                           const uint32_t* prime_partner_buf, uint32_t* xbuf,
+                                           const uint32_t* half_partner_xbuf, const uint2* tws, const uint2* gtw2,
+                                           int lane) {
+  constexpr uint32_t P = Prime<PR>::P, PINV = Prime<PR>::PINV;
+  const uint32_t* bk_i = I.bk;
+  for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
+    const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
+    if (ab == 0) continue;  // the same decision in all four wavefronts: abar is shared
+    // Three products of transform values (< 4P) and key residues (< P) per
+    // output: below 12 P^2 < 2P * 2^32, so one reduction gives [0, 2P).
+    uint64_t m0[16], m1[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;
+    {
+      const uint32_t* poly = acc + H * RING_N;
+      uint32_t D[16], src[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t j = r * 64 + lane;
+        src[r] = poly[((j + 2048u - ab) & 2047u) & 1023u];  // coefficient j of X^ab p is +-p[j - ab]
+        D[r] = poly[j];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
+        D[r] = (s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET;
+      }
+#pragma unroll 1
+      for (int lev = 0; lev < ELL; ++lev) {
+        const g_u32* k0 = (const g_u32*)(bk_i + (size_t)((H * ELL + lev) * 4 + PR) * RING_N);
+        uint32_t b0[16], b1[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          b0[r] = k0[r * 64 + lane];
+          b1[r] = k0[2 * RING_N + r * 64 + lane];
+        }
+        const int shift = 32 - BG_BIT * (lev + 1);
+        uint32_t x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = ((D[r] >> shift) & 127u) + (P - 64);
+        ntt_fwd1<PR>(x, buf, tws, gtw2, lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          m0[r] += (uint64_t)x[r] * b0[r];
+          m1[r] += (uint64_t)x[r] * b1[r];
+        }
+      }
+    }
+    // Hand the partial of output 1-H to the other half; keep output H's.
+    uint32_t x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      xbuf[r * 64 + lane] = redc(H ? m0[r] : m1[r], P, PINV);  // [0, 2P)
+      x[r] = redc(H ? m1[r] : m0[r], P, PINV);
+    }
+    __syncthreads();  // B1
+    uint32_t oth[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) oth[r] = half_partner_xbuf[r * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = csub(x[r] + oth[r], 2 * P);  // [0, 2P)
+    ntt_inv1<PR>(x, buf, tws, gtw2, lane);
+    // Wave (0, H) lifts registers 0..7, wave (1, H) registers 8..15: each parks
+    // the half the other one lifts.
+    wave_lds_sync();  // the transform's last reads of buf are done
+    constexpr int MINE = PR * 8, THEIRS = 8 - PR * 8;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[(THEIRS + r) * 64 + lane] = csub(x[THEIRS + r], P);
+    __syncthreads();  // B2
+    uint32_t* poly = acc + H * RING_N;
+    uint32_t old[8], o2[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      old[r] = poly[(MINE + r) * 64 + lane];
+      o2[r] = prime_partner_buf[(MINE + r) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t mine = csub(x[MINE + r], P);
+      poly[(MINE + r) * 64 + lane] = old[r] + (PR == 0 ? crt_lift_u32(mine, o2[r]) : crt_lift_u32(o2[r], mine));
+    }
+    __syncthreads();  // B3
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void br4_kernel(
+    const BrItem* __restrict__ items, uint32_t count, const Tw* __restrict__ tw_fwd) {
+  __shared__ uint2 s_tw[2][RING_N];      // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
+  __shared__ uint32_t s_buf[4][RING_N];  // per wavefront: transpose scratch, then CRT hand-over
+  __shared__ uint32_t s_x[4][RING_N];    // per wavefront: partial sum handed to the other half
+  __shared__ uint32_t s_acc[2][RING_N];  // accumulator (A, B), coefficient order
+  __shared__ uint16_t s_abar[CT_n + 1];  // modulus-switched input
+  for (int e = 16 + threadIdx.x; e < RING_N; e += blockDim.x) {  // stages 4..9 (entries 16..1023)
+    const int S = 31 - __builtin_clz(e);
+    const int slot = (1 << S) + tw_perm(S, e - (1 << S));
+    const Tw w = tw_fwd[e];
+    s_tw[0][slot] = make_uint2(w.x, w.y);
+    s_tw[1][slot] = make_uint2(w.z, w.w);
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint2* gtw2 = reinterpret_cast<const uint2*>(tw_fwd);
+  uint32_t* acc = s_acc[0];
+  for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const BrItem I = items[it];
+    __syncthreads();  // the previous item's readers of acc and abar are done
+    const g_u32* in_a = (const g_u32*)I.a;
+    const g_u32* in_b = (const g_u32*)I.b;
+    for (int w = threadIdx.x; w < CT_n; w += 256) {
+      uint32_t x = (uint32_t)I.ca * in_a[w];
+      if (I.b) x += (uint32_t)I.cb * in_b[w];
+      for (uint32_t t = 0; t < I.n_more; ++t) x += (uint32_t)I.cm * ((const g_u32*)I.more[t])[w];
+      if (w == LWE_n) x += I.cst;
+      s_abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
+    }
+    __syncthreads();
+    // acc = (0, X^(-bbar) * mu * (1 + X + ... + X^1023)): waves 0, 1 write A (halves), 2, 3 write B.
+    const uint32_t bbar = __builtin_amdgcn_readfirstlane(s_abar[LWE_n]);
+    const uint32_t rot = (2048u - bbar) & 2047u;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t j = ((wave & 1) * 8 + r) * 64 + lane;
+      const bool neg = (j < (rot & 1023u)) != (rot >= 1024u);
+      acc[(wave >> 1) * RING_N + j] = (wave >> 1) == 0 ? 0u : (neg ? (0u - I.mu) : I.mu);
+    }
+    __syncthreads();
+    switch (wave) {
+      case 0: br4_rotate<0, 0>(I, acc, s_abar, s_buf[0], s_buf[1], s_x[0], s_x[2], s_tw[0], gtw2, lane); break;
+      case 1: br4_rotate<1, 0>(I, acc, s_abar, s_buf[1], s_buf[0], s_x[1], s_x[3], s_tw[1], gtw2, lane); break;
+      case 2: br4_rotate<0, 1>(I, acc, s_abar, s_buf[2], s_buf[3], s_x[2], s_x[0], s_tw[0], gtw2, lane); break;
+      default: br4_rotate<1, 1>(I, acc, s_abar, s_buf[3], s_buf[2], s_x[3], s_x[1], s_tw[1], gtw2, lane); break;
+    }
+    for (int j = threadIdx.x; j < RING_N; j += 256) {
+      const uint32_t a = acc[j];
+      if (j == 0) I.out[0] = a;
+      else I.out[RING_N - j] = 0u - a;
+    }
+    if (threadIdx.x == 0) I.out[RING_N] = acc[RING_N];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Key switching: a block handles T gates that share one key; each of the
 // block's 320 threads owns two of the 640 padded output words.
 // ---------------------------------------------------------------------------
@@ -596,6 +756,13 @@ int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_
   if (count == 0) return 0;
   if (blocks == 0 || blocks > count) blocks = count;
   hipLaunchKernelGGL(br2_kernel, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd);
+  return (int)hipGetLastError();
+}
+
+int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream) {
+  if (count == 0) return 0;
+  if (blocks == 0 || blocks > count) blocks = count;
+  hipLaunchKernelGGL(br4_kernel, dim3(blocks), dim3(256), 0, S(stream), items, count, tw_fwd);
   return (int)hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ struct vlp_ctx {
   std::string err;
   uint4* tw_fwd = nullptr;  // device twiddle table
   int num_cus = 256;
-  vlp_tuning tune{4, 4, 4, 1};
+  vlp_tuning tune{4, 4, 4, 0};
   // Grow-only scratch for the elementwise calls.
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -142,7 +142,6 @@ bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
   return pa < pb + bn && pb < pa + an;
 }
 
-size_t br_blocks(const vlp_ctx* ctx) { return (size_t)ctx->num_cus * ctx->tune.br_blocks_per_cu; }
 
 int mark_begin(vlp_ctx* ctx);
 void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
@@ -154,16 +153,30 @@ void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
 // re-fetch the key (measured: ~0.5 MB vs up to ~36 MB of key traffic per
 // blind rotation).
 int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
-  const bool split = ctx->tune.br_prime_split != 0;
-  const uint32_t waves = split ? 1 : ctx->tune.br_waves_per_block, blocks = (uint32_t)br_blocks(ctx);
-  const uint32_t chunk = blocks * waves;  // rotations per launch
-  for (uint32_t first = 0; first < count; first += chunk) {
-    const uint32_t n = std::min(chunk, count - first);
+  const uint32_t mode = ctx->tune.br_waves_per_rotation, bpc = ctx->tune.br_blocks_per_cu;
+  const uint32_t cus = (uint32_t)ctx->num_cus;
+  const uint32_t small = cus * std::max(1u, bpc / 2);  // rotations a four-wavefront launch holds
+  for (uint32_t first = 0; first < count;) {
+    const uint32_t rem = count - first;
+    uint32_t n;
+    int e;
     const int m = mark_begin(ctx);
-    const int e = split ? launch_br2(items + first, n, ctx->tw_fwd, blocks, ctx->stream)
-                        : launch_br(items + first, n, ctx->tw_fwd, waves, blocks, ctx->stream);
+    if (mode == 4 || (mode == 0 && rem <= small)) {
+      const uint32_t blocks = mode == 4 ? cus * bpc : small;
+      n = std::min(blocks, rem);
+      e = launch_br4(items + first, n, ctx->tw_fwd, blocks, ctx->stream);
+    } else if (mode == 1) {
+      const uint32_t waves = ctx->tune.br_waves_per_block, blocks = cus * bpc;
+      n = std::min(blocks * waves, rem);
+      e = launch_br(items + first, n, ctx->tw_fwd, waves, blocks, ctx->stream);
+    } else {
+      const uint32_t blocks = cus * bpc;
+      n = std::min(blocks, rem);
+      e = launch_br2(items + first, n, ctx->tw_fwd, blocks, ctx->stream);
+    }
     mark_end(ctx, m, 0, n);
     if (e != 0) return e;
+    first += n;
   }
   return 0;
 }
@@ -349,7 +362,8 @@ extern "C" vlp_status vlp_set_tuning(vlp_ctx* ctx, const vlp_tuning* t) {
   if (!(w == 1 || w == 2 || w == 4 || w == 8)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2, 4 or 8");
   if (t->br_blocks_per_cu < 1 || t->br_blocks_per_cu > 64) return fail(ctx, VLP_EINVAL, "br_blocks_per_cu out of [1, 64]");
   if (!(g == 4 || g == 8 || g == 16)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 4, 8 or 16");
-  if (t->br_prime_split > 1) return fail(ctx, VLP_EINVAL, "br_prime_split must be 0 or 1");
+  const uint32_t r = t->br_waves_per_rotation;
+  if (!(r == 0 || r == 1 || r == 2 || r == 4)) return fail(ctx, VLP_EINVAL, "br_waves_per_rotation must be 0, 1, 2 or 4");
   ctx->tune = *t;
   return VLP_OK;
 }

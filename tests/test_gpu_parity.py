@@ -173,12 +173,14 @@ def test_step_merges_programs(gpu, oracle_keys):
         vlp.vlp_program_destroy(ctx.ctx, p)
 
 
-@pytest.mark.parametrize("split,waves,blocks", [(0, 1, 4), (0, 2, 2), (0, 4, 1), (0, 8, 1), (1, 1, 4), (1, 1, 1)])
-def test_bootstrap_parity_every_launch_shape(gpu, oracle_keys, split, waves, blocks):
+@pytest.mark.parametrize("per_rot,waves,blocks", [(1, 1, 4), (1, 2, 2), (1, 4, 1), (1, 8, 1), (2, 4, 4), (2, 4, 1),
+                                                  (4, 4, 2), (4, 4, 1), (0, 4, 4)])
+def test_bootstrap_parity_every_launch_shape(gpu, oracle_keys, per_rot, waves, blocks):
     """Each blind-rotation kernel and workgroup shape matches the oracle word
-    for word: the 8-wave form has its own register plan (key read at use,
-    32-bit accumulators), the split form runs two wavefronts per rotation, one
-    per prime.  41 items leave the last one-wavefront workgroup partly idle."""
+    for word: one wavefront per rotation (the 8-wave form has its own register
+    plan: key read at use, 32-bit accumulators), two (one per prime) and four
+    (prime x accumulator half), and the automatic choice.  41 items leave the
+    last one-wavefront workgroup partly idle."""
     vlp, ctx, ks = gpu
     B = 41
     ins = _rand_words(11, (B, O.n + 1))
@@ -188,13 +190,13 @@ def test_bootstrap_parity_every_launch_shape(gpu, oracle_keys, split, waves, blo
     d_out = ctx.empty(B, O.N + 1)
     old = vlp.vlp_get_tuning(ctx.ctx)
     try:
-        vlp.vlp_set_tuning(ctx.ctx, waves, blocks, old.ks_gates_per_block, split)
+        vlp.vlp_set_tuning(ctx.ctx, waves, blocks, old.ks_gates_per_block, per_rot)
         vlp.vlp_bootstrap(ctx.ctx, ks, d_in, d_out, MU, B)
         ctx.sync()
     finally:
         vlp.vlp_set_tuning(ctx.ctx, old.br_waves_per_block, old.br_blocks_per_cu, old.ks_gates_per_block,
-                           old.br_prime_split)
+                           old.br_waves_per_rotation)
     got = ctx.to_host(d_out)
     want = _pool(lambda c: O.bootstrap_wo_ks(oracle_keys, c, MU), list(ins))
     for b in range(B):
-        assert np.array_equal(got[b], want[b]), (split, waves, blocks, b)
+        assert np.array_equal(got[b], want[b]), (per_rot, waves, blocks, b)
