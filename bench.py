@@ -47,7 +47,7 @@ PEAK_MODMUL = VALU_LANE_OPS / OPS_PER_MODMUL  # 2.4576e12 modmul/s
 # copy-calibrated), valid only for the kernel sources it was measured on
 # (their sha256 prefix) and the launch shape it was measured with.
 TRAFFIC_MEASURED = {"kernel_sha": "f1611892a4f28ae7", "bytes_per_launch": 1.65059e+09,
-                    "launch": {"br_waves_per_rotation": 2, "br_waves_per_block": 4, "br_blocks_per_cu": 4,
+                    "launch": {"br_waves_per_rotation": 2, "br_rotations_per_block": 1, "br_blocks_per_cu": 4,
                                "ks_gates_per_block": 4}}
 KERNEL_SOURCES = ("kernels.hip", "wave_ntt.h", "rns.h", "vlp_api.cpp")
 
@@ -312,7 +312,8 @@ def main():
     ap.add_argument("--records", type=int, default=0, help="override the record count of every program")
     ap.add_argument("--agg-k", type=int, default=0, help="aggregate with k-input XORs (2..16) where l_S > 0")
     ap.add_argument("--tuned", action="store_true", help="apply the cached autotuner result")
-    ap.add_argument("--br-waves", type=int, default=0, help="waves per blind-rotation workgroup (1, 2, 4, 8)")
+    ap.add_argument("--br-rotations-per-block", type=int, default=0,
+                    help="blind rotations per workgroup (1, 2, 4; 8 with one wavefront per rotation)")
     ap.add_argument("--br-blocks", type=int, default=0, help="blind-rotation workgroups per CU the grid is sized for")
     ap.add_argument("--br-waves-per-rotation", type=int, default=-1, choices=(-1, 0, 1, 2, 4),
                     help="wavefronts per blind rotation (0: automatic by launch size)")
@@ -368,13 +369,14 @@ def main():
     if args.tuned:
         from paper_2506_12761_amd import autotune
         log("cached tuning applied: %s" % autotune.load_cached(ctx, args.workload))
-    if args.br_waves or args.br_blocks or args.br_waves_per_rotation >= 0:
+    if args.br_rotations_per_block or args.br_blocks or args.br_waves_per_rotation >= 0:
         t = vlp.vlp_get_tuning(ctx.ctx)
-        vlp.vlp_set_tuning(ctx.ctx, args.br_waves or t.br_waves_per_block, args.br_blocks or t.br_blocks_per_cu,
+        vlp.vlp_set_tuning(ctx.ctx, args.br_rotations_per_block or t.br_rotations_per_block,
+                           args.br_blocks or t.br_blocks_per_cu,
                            t.ks_gates_per_block,
                            args.br_waves_per_rotation if args.br_waves_per_rotation >= 0 else t.br_waves_per_rotation)
     t = vlp.vlp_get_tuning(ctx.ctx)
-    launch = {"br_waves_per_rotation": t.br_waves_per_rotation, "br_waves_per_block": t.br_waves_per_block,
+    launch = {"br_waves_per_rotation": t.br_waves_per_rotation, "br_rotations_per_block": t.br_rotations_per_block,
               "br_blocks_per_cu": t.br_blocks_per_cu, "ks_gates_per_block": t.ks_gates_per_block}
     progs, keep = [], []
     for k, p in enumerate(specs):

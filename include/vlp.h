@@ -215,25 +215,27 @@ vlp_status vlp_program_counts(const vlp_program *prog, uint64_t *gates, uint64_t
 vlp_status vlp_program_destroy(vlp_program *prog);
 
 /* ---- Tuning knobs of the batched kernels (picked by the autotuner).
- * br_waves_per_rotation: wavefronts per blind rotation:
- *                     1 = both RNS primes in one wavefront, br_waves_per_block
- *                         of them per workgroup;
- *                     2 = one wavefront per prime, one rotation per workgroup;
- *                     4 = one per prime and accumulator half (half the
- *                         latency of 2 per rotation, half the rotations in
- *                         flight);
- *                     0 = automatic (default): launches of at most
- *                         br_blocks_per_cu / 2 rotations per CU use 4, larger
- *                         ones 2, in rounds of br_blocks_per_cu rotations per
- *                         CU, a short last round again 4
- * br_waves_per_block: (1 wavefront per rotation) wavefronts per workgroup
- *                     (1, 2, 4, 8; 8 = two per SIMD at half the registers each)
- * br_blocks_per_cu  : resident workgroups per compute unit a launch is sized
- *                     for (1..64); one launch covers that many rotations per
- *                     CU times the rotations per workgroup
- * ks_gates_per_block: gates sharing one pass over the key-switching key (4, 8, 16) */
+ * br_waves_per_rotation : wavefronts per blind rotation:
+ *                          1 = both RNS primes in one wavefront;
+ *                          2 = one wavefront per prime;
+ *                          4 = one per prime and accumulator half (half the
+ *                              latency of 2 per rotation, half the rotations
+ *                              in flight; one rotation per workgroup);
+ *                          0 = automatic (default): launches of at most 2
+ *                              rotations per CU use 4 (2 workgroups per CU),
+ *                              larger ones 2 in full rounds, a short last
+ *                              round again 4
+ * br_rotations_per_block: rotations per workgroup (1 wavefront per rotation:
+ *                          1, 2, 4, 8 -- 8 puts two on a SIMD at half the
+ *                          registers each; 2 wavefronts per rotation: 1, 2, 4
+ *                          -- the rotations of a workgroup advance in
+ *                          lockstep and share key reads; 4: 1)
+ * br_blocks_per_cu      : workgroups per compute unit a launch is sized for
+ *                          (1..64); one launch covers br_blocks_per_cu x
+ *                          br_rotations_per_block rotations per CU
+ * ks_gates_per_block    : gates sharing one pass over the key-switching key (4, 8, 16) */
 typedef struct {
-    uint32_t br_waves_per_block;
+    uint32_t br_rotations_per_block;
     uint32_t br_blocks_per_cu;
     uint32_t ks_gates_per_block;
     uint32_t br_waves_per_rotation;

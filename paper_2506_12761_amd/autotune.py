@@ -2,8 +2,8 @@
 
 Two sweeps:
   * launch shape -- wavefronts per blind rotation (1, 2, 4 or automatic),
-    waves per one-wavefront workgroup, workgroups per CU a launch is sized
-    for, gates per key-switching workgroup -- timed
+    rotations per workgroup, workgroups per CU a launch is sized for, gates
+    per key-switching workgroup -- timed
     on a caller-supplied program (one full pass each), the fastest is set on
     the context and cached per device and workload;
   * batch size -- blind rotations per launch from 256 to 16,384, timed with
@@ -20,15 +20,15 @@ from . import vlp
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
-# (wavefronts per rotation, waves per workgroup, workgroups per CU, gates per
-# key-switching workgroup); 0 wavefronts per rotation = automatic by launch size
-SHAPES = ([(1, w, b, k) for w in (1, 2, 4, 8) for b in (1, 2, 4) for k in (4, 8, 16) if w * b <= 8]
-          + [(r, 4, b, k) for r in (0, 2) for b in (2, 4, 8) for k in (4, 8, 16)]
-          + [(4, 4, b, k) for b in (1, 2, 4) for k in (4, 8, 16)])
+# (wavefronts per rotation, rotations per workgroup, workgroups per CU, gates
+# per key-switching workgroup); 0 wavefronts per rotation = automatic by launch size
+SHAPES = ([(1, w, b, k) for w in (1, 2, 4, 8) for b in (1, 2, 4) for k in (4, 8) if w * b <= 8]
+          + [(r, q, b, k) for r in (0, 2) for (q, b) in ((1, 4), (2, 2), (4, 1)) for k in (4, 8, 16)]
+          + [(4, 1, b, k) for b in (1, 2) for k in (4, 8)])
 
 
 def _apply(ctx, best: dict) -> None:
-    vlp.vlp_set_tuning(ctx.ctx, best["br_waves_per_block"], best["br_blocks_per_cu"], best["ks_gates_per_block"],
+    vlp.vlp_set_tuning(ctx.ctx, best["br_rotations_per_block"], best["br_blocks_per_cu"], best["ks_gates_per_block"],
                        best.get("br_waves_per_rotation", 0))
 
 
@@ -47,10 +47,10 @@ def tune_launch(ctx, prog, shapes=SHAPES, log=None) -> dict:
     for (r, w, b, k) in shapes:
         vlp.vlp_set_tuning(ctx.ctx, w, b, k, r)
         dt = _time_program(ctx, prog)
-        results.append({"br_waves_per_rotation": r, "br_waves_per_block": w, "br_blocks_per_cu": b,
+        results.append({"br_waves_per_rotation": r, "br_rotations_per_block": w, "br_blocks_per_cu": b,
                         "ks_gates_per_block": k, "s": dt})
         if log:
-            log("tune per-rotation=%d w=%d b=%d k=%d: %.3f s" % (r, w, b, k, dt))
+            log("tune waves/rotation=%d rotations/block=%d blocks/CU=%d ks gates/block=%d: %.3f s" % (r, w, b, k, dt))
     best = min(results, key=lambda r: r["s"])
     _apply(ctx, best)
     return {"best": best, "all": results}

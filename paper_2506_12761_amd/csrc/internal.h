@@ -61,8 +61,9 @@ int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t
 // ServerEnc over a flat [count][631] array; out == pk runs in place.
 int launch_server_enc(const uint32_t* pk, uint32_t* out, size_t count, const int64_t* vals, const uint8_t* bytes,
                       uint32_t l, void* stream);
-// Two wavefronts per rotation (one per prime), one rotation per workgroup.
-int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream);
+// Two wavefronts per rotation (one per prime), rot_per_block (1, 2, 4) rotations per workgroup.
+int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t rot_per_block, uint32_t blocks,
+               void* stream);
 // Four wavefronts per rotation (prime x accumulator half), one rotation per workgroup.
 int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream);
 int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream);

@@ -239,14 +239,17 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
 // inverse transforms (each hands the other the residues of the output
 // polynomial that the other lifts) and after the accumulator update.
 // ---------------------------------------------------------------------------
-template <int PR>
+// SKIP: steps with abar_i = 0 (X^0 acc - acc = 0, an exact no-op) are skipped;
+// workgroups holding several rotations run them all, so that every wavefront
+// of the workgroup meets the same barriers.
+template <int PR, bool SKIP>
 __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const uint16_t* abar, uint32_t* buf,
                                            const uint32_t* other_buf, const uint2* tws, const uint2* gtw2, int lane) {
   constexpr uint32_t P = Prime<PR>::P, PINV = Prime<PR>::PINV;
   const uint32_t* bk_i = I.bk;
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
     const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
-    if (ab == 0) continue;  // the same decision in both wavefronts: abar is shared
+    if (SKIP && ab == 0) continue;  // the same decision in both wavefronts: abar is shared
     // 64-bit accumulators of the two output polynomials mod P: six products of
     // transform values (< 4P) and key residues (< P) stay below 4P * 2^32, so
     // one reduction at the end gives [0, 4P) and a conditional subtract [0, 2P).
@@ -327,12 +330,17 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
   }
 }
 
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void br2_kernel(const BrItem* __restrict__ items, uint32_t count,
-                                                  const Tw* __restrict__ tw_fwd) {
-  __shared__ uint2 s_tw[2][RING_N];            // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
-  __shared__ uint32_t s_buf[2][RING_N];        // per wavefront: transpose scratch, then parked residues
-  __shared__ uint32_t s_acc[2][RING_N];        // accumulator (A, B), coefficient order
-  __shared__ uint16_t s_abar[CT_n + 1];        // modulus-switched input
+// ROT rotations per workgroup (2 * ROT wavefronts): with ROT > 1 the
+// rotations of a workgroup advance in lockstep (their wavefronts share every
+// barrier), so they read each key row at the same time; a partial last
+// workgroup repeats the last item in its idle rotations and writes nothing.
+template <int ROT>
+__global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) void br2_kernel(
+    const BrItem* __restrict__ items, uint32_t count, const Tw* __restrict__ tw_fwd) {
+  __shared__ uint2 s_tw[2][RING_N];              // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
+  __shared__ uint32_t s_buf[2 * ROT][RING_N];    // per wavefront: transpose scratch, then parked residues
+  __shared__ uint32_t s_acc[ROT][2][RING_N];     // per rotation: accumulator (A, B), coefficient order
+  __shared__ uint16_t s_abar[ROT][CT_n + 1];     // per rotation: modulus-switched input
   for (int e = 16 + threadIdx.x; e < RING_N; e += blockDim.x) {  // stages 4..9 (entries 16..1023)
     const int S = 31 - __builtin_clz(e);
     const int slot = (1 << S) + tw_perm(S, e - (1 << S));
@@ -342,43 +350,49 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void b
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rot_i = wave >> 1, pr = wave & 1, t = threadIdx.x & 127;  // t: thread within the rotation's pair
   const uint2* gtw2 = reinterpret_cast<const uint2*>(tw_fwd);
-  uint32_t* acc = s_acc[0];
-  for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
-    const BrItem I = items[it];
+  uint32_t* acc = s_acc[rot_i][0];
+  uint16_t* abar = s_abar[rot_i];
+  for (uint32_t g = blockIdx.x; g * ROT < count; g += gridDim.x) {
+    const uint32_t idx = g * ROT + rot_i;
+    const bool active = idx < count;
+    const BrItem I = items[active ? idx : count - 1];
     __syncthreads();  // the previous item's readers of acc and abar are done
     const g_u32* in_a = (const g_u32*)I.a;
     const g_u32* in_b = (const g_u32*)I.b;
-    for (int w = threadIdx.x; w < CT_n; w += 128) {
+    for (int w = t; w < CT_n; w += 128) {
       uint32_t x = (uint32_t)I.ca * in_a[w];
       if (I.b) x += (uint32_t)I.cb * in_b[w];
-      for (uint32_t t = 0; t < I.n_more; ++t) x += (uint32_t)I.cm * ((const g_u32*)I.more[t])[w];
+      for (uint32_t k = 0; k < I.n_more; ++k) x += (uint32_t)I.cm * ((const g_u32*)I.more[k])[w];
       if (w == LWE_n) x += I.cst;
-      s_abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
+      abar[w] = (uint16_t)((x + (1u << 20)) >> 21);
     }
     __syncthreads();
-    // acc = (0, X^(-bbar) * mu * (1 + X + ... + X^1023)): wave 0 writes A, wave 1 B.
-    const uint32_t bbar = __builtin_amdgcn_readfirstlane(s_abar[LWE_n]);
+    // acc = (0, X^(-bbar) * mu * (1 + X + ... + X^1023)): wave 0 of the pair writes A, wave 1 B.
+    const uint32_t bbar = __builtin_amdgcn_readfirstlane(abar[LWE_n]);
     const uint32_t rot = (2048u - bbar) & 2047u;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const uint32_t j = r * 64 + lane;
       const bool neg = (j < (rot & 1023u)) != (rot >= 1024u);
-      acc[wave * RING_N + j] = wave == 0 ? 0u : (neg ? (0u - I.mu) : I.mu);
+      acc[pr * RING_N + j] = pr == 0 ? 0u : (neg ? (0u - I.mu) : I.mu);
     }
     __syncthreads();
-    if (wave == 0)
-      br2_rotate<0>(I, acc, s_abar, s_buf[0], s_buf[1], s_tw[0], gtw2, lane);
+    if (pr == 0)
+      br2_rotate<0, ROT == 1>(I, acc, abar, s_buf[2 * rot_i], s_buf[2 * rot_i + 1], s_tw[0], gtw2, lane);
     else
-      br2_rotate<1>(I, acc, s_abar, s_buf[1], s_buf[0], s_tw[1], gtw2, lane);
+      br2_rotate<1, ROT == 1>(I, acc, abar, s_buf[2 * rot_i + 1], s_buf[2 * rot_i], s_tw[1], gtw2, lane);
     // SampleExtract: a'_0 = A_0, a'_j = -A_(N-j), b' = B_0 (the last update is
     // visible after the rotation's closing barrier, or the one above if no step ran).
-    for (int j = threadIdx.x; j < RING_N; j += 128) {
-      const uint32_t a = acc[j];
-      if (j == 0) I.out[0] = a;
-      else I.out[RING_N - j] = 0u - a;
+    if (active) {
+      for (int j = t; j < RING_N; j += 128) {
+        const uint32_t a = acc[j];
+        if (j == 0) I.out[0] = a;
+        else I.out[RING_N - j] = 0u - a;
+      }
+      if (t == 0) I.out[RING_N] = acc[RING_N];
     }
-    if (threadIdx.x == 0) I.out[RING_N] = acc[RING_N];
   }
 }
 
@@ -752,10 +766,17 @@ int launch_br(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t
   return (int)hipGetLastError();
 }
 
-int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream) {
+int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t rot_per_block, uint32_t blocks,
+               void* stream) {
   if (count == 0) return 0;
-  if (blocks == 0 || blocks > count) blocks = count;
-  hipLaunchKernelGGL(br2_kernel, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd);
+  const uint32_t need = (count + rot_per_block - 1) / rot_per_block;
+  if (blocks == 0 || blocks > need) blocks = need;
+  switch (rot_per_block) {
+    case 1: hipLaunchKernelGGL(br2_kernel<1>, dim3(blocks), dim3(128), 0, S(stream), items, count, tw_fwd); break;
+    case 2: hipLaunchKernelGGL(br2_kernel<2>, dim3(blocks), dim3(256), 0, S(stream), items, count, tw_fwd); break;
+    case 4: hipLaunchKernelGGL(br2_kernel<4>, dim3(blocks), dim3(512), 0, S(stream), items, count, tw_fwd); break;
+    default: return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 

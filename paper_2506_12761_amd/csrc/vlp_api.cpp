@@ -24,7 +24,7 @@ struct vlp_ctx {
   std::string err;
   uint4* tw_fwd = nullptr;  // device twiddle table
   int num_cus = 256;
-  vlp_tuning tune{4, 4, 4, 0};
+  vlp_tuning tune{4, 1, 4, 0};
   // Grow-only scratch for the elementwise calls.
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -154,8 +154,8 @@ void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
 // blind rotation).
 int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
   const uint32_t mode = ctx->tune.br_waves_per_rotation, bpc = ctx->tune.br_blocks_per_cu;
-  const uint32_t cus = (uint32_t)ctx->num_cus;
-  const uint32_t small = cus * std::max(1u, bpc / 2);  // rotations a four-wavefront launch holds
+  const uint32_t rpb = ctx->tune.br_rotations_per_block, cus = (uint32_t)ctx->num_cus;
+  const uint32_t small = cus * 2;  // rotations one round of the four-wavefront kernel holds
   for (uint32_t first = 0; first < count;) {
     const uint32_t rem = count - first;
     uint32_t n;
@@ -166,13 +166,13 @@ int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
       n = std::min(blocks, rem);
       e = launch_br4(items + first, n, ctx->tw_fwd, blocks, ctx->stream);
     } else if (mode == 1) {
-      const uint32_t waves = ctx->tune.br_waves_per_block, blocks = cus * bpc;
-      n = std::min(blocks * waves, rem);
-      e = launch_br(items + first, n, ctx->tw_fwd, waves, blocks, ctx->stream);
+      const uint32_t blocks = cus * bpc;
+      n = std::min(blocks * rpb, rem);
+      e = launch_br(items + first, n, ctx->tw_fwd, rpb, blocks, ctx->stream);
     } else {
       const uint32_t blocks = cus * bpc;
-      n = std::min(blocks, rem);
-      e = launch_br2(items + first, n, ctx->tw_fwd, blocks, ctx->stream);
+      n = std::min(blocks * rpb, rem);
+      e = launch_br2(items + first, n, ctx->tw_fwd, rpb, blocks, ctx->stream);
     }
     mark_end(ctx, m, 0, n);
     if (e != 0) return e;
@@ -358,12 +358,13 @@ extern "C" vlp_status vlp_get_tuning(const vlp_ctx* ctx, vlp_tuning* t) {
 
 extern "C" vlp_status vlp_set_tuning(vlp_ctx* ctx, const vlp_tuning* t) {
   if (!ctx || !t) return VLP_EINVAL;
-  const uint32_t w = t->br_waves_per_block, g = t->ks_gates_per_block;
-  if (!(w == 1 || w == 2 || w == 4 || w == 8)) return fail(ctx, VLP_EINVAL, "br_waves_per_block must be 1, 2, 4 or 8");
+  const uint32_t rpb = t->br_rotations_per_block, g = t->ks_gates_per_block, r = t->br_waves_per_rotation;
+  if (!(r == 0 || r == 1 || r == 2 || r == 4)) return fail(ctx, VLP_EINVAL, "br_waves_per_rotation must be 0, 1, 2 or 4");
+  const bool rpb_ok = r == 1 ? (rpb == 1 || rpb == 2 || rpb == 4 || rpb == 8)
+                             : (r == 4 ? rpb == 1 : (rpb == 1 || rpb == 2 || rpb == 4));
+  if (!rpb_ok) return fail(ctx, VLP_EINVAL, "br_rotations_per_block %u not available with %u wavefronts per rotation", rpb, r);
   if (t->br_blocks_per_cu < 1 || t->br_blocks_per_cu > 64) return fail(ctx, VLP_EINVAL, "br_blocks_per_cu out of [1, 64]");
   if (!(g == 4 || g == 8 || g == 16)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 4, 8 or 16");
-  const uint32_t r = t->br_waves_per_rotation;
-  if (!(r == 0 || r == 1 || r == 2 || r == 4)) return fail(ctx, VLP_EINVAL, "br_waves_per_rotation must be 0, 1, 2 or 4");
   ctx->tune = *t;
   return VLP_OK;
 }

@@ -57,7 +57,7 @@ class vlp_kernel_stats(ctypes.Structure):
 
 
 class vlp_tuning(ctypes.Structure):
-    _fields_ = [("br_waves_per_block", ctypes.c_uint32), ("br_blocks_per_cu", ctypes.c_uint32),
+    _fields_ = [("br_rotations_per_block", ctypes.c_uint32), ("br_blocks_per_cu", ctypes.c_uint32),
                 ("ks_gates_per_block", ctypes.c_uint32), ("br_waves_per_rotation", ctypes.c_uint32)]
 
 
@@ -249,9 +249,9 @@ def vlp_get_tuning(ctx) -> vlp_tuning:
     return t
 
 
-def vlp_set_tuning(ctx, br_waves_per_block: int, br_blocks_per_cu: int, ks_gates_per_block: int,
+def vlp_set_tuning(ctx, br_rotations_per_block: int, br_blocks_per_cu: int, ks_gates_per_block: int,
                    br_waves_per_rotation: int = 0) -> None:
-    t = vlp_tuning(br_waves_per_block, br_blocks_per_cu, ks_gates_per_block, br_waves_per_rotation)
+    t = vlp_tuning(br_rotations_per_block, br_blocks_per_cu, ks_gates_per_block, br_waves_per_rotation)
     _check(ctx, lib().vlp_set_tuning(ctx, ctypes.byref(t)))
 
 

@@ -173,14 +173,15 @@ def test_step_merges_programs(gpu, oracle_keys):
         vlp.vlp_program_destroy(ctx.ctx, p)
 
 
-@pytest.mark.parametrize("per_rot,waves,blocks", [(1, 1, 4), (1, 2, 2), (1, 4, 1), (1, 8, 1), (2, 4, 4), (2, 4, 1),
-                                                  (4, 4, 2), (4, 4, 1), (0, 4, 4)])
-def test_bootstrap_parity_every_launch_shape(gpu, oracle_keys, per_rot, waves, blocks):
+@pytest.mark.parametrize("per_rot,rpb,blocks", [(1, 1, 4), (1, 2, 2), (1, 4, 1), (1, 8, 1), (2, 1, 4), (2, 1, 1),
+                                                (2, 2, 2), (2, 4, 1), (4, 1, 2), (4, 1, 1), (0, 4, 1), (0, 1, 4)])
+def test_bootstrap_parity_every_launch_shape(gpu, oracle_keys, per_rot, rpb, blocks):
     """Each blind-rotation kernel and workgroup shape matches the oracle word
     for word: one wavefront per rotation (the 8-wave form has its own register
-    plan: key read at use, 32-bit accumulators), two (one per prime) and four
-    (prime x accumulator half), and the automatic choice.  41 items leave the
-    last one-wavefront workgroup partly idle."""
+    plan: key read at use, 32-bit accumulators), two (one per prime; 1, 2 or 4
+    rotations per workgroup in lockstep) and four (prime x accumulator half),
+    and the automatic choice.  41 items leave the last workgroup partly idle
+    (a lockstep workgroup then repeats an item without writing it)."""
     vlp, ctx, ks = gpu
     B = 41
     ins = _rand_words(11, (B, O.n + 1))
@@ -190,13 +191,13 @@ def test_bootstrap_parity_every_launch_shape(gpu, oracle_keys, per_rot, waves, b
     d_out = ctx.empty(B, O.N + 1)
     old = vlp.vlp_get_tuning(ctx.ctx)
     try:
-        vlp.vlp_set_tuning(ctx.ctx, waves, blocks, old.ks_gates_per_block, per_rot)
+        vlp.vlp_set_tuning(ctx.ctx, rpb, blocks, old.ks_gates_per_block, per_rot)
         vlp.vlp_bootstrap(ctx.ctx, ks, d_in, d_out, MU, B)
         ctx.sync()
     finally:
-        vlp.vlp_set_tuning(ctx.ctx, old.br_waves_per_block, old.br_blocks_per_cu, old.ks_gates_per_block,
+        vlp.vlp_set_tuning(ctx.ctx, old.br_rotations_per_block, old.br_blocks_per_cu, old.ks_gates_per_block,
                            old.br_waves_per_rotation)
     got = ctx.to_host(d_out)
     want = _pool(lambda c: O.bootstrap_wo_ks(oracle_keys, c, MU), list(ins))
     for b in range(B):
-        assert np.array_equal(got[b], want[b]), (per_rot, waves, blocks, b)
+        assert np.array_equal(got[b], want[b]), (per_rot, rpb, blocks, b)
