@@ -557,32 +557,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 }
 
 // ---------------------------------------------------------------------------
-// Key switching: a block handles T gates that share one key; each of the
-// block's 320 threads owns two of the 640 padded output words.
+// Key switching: a block handles T gates that share each key row it reads,
+// over 1/SPLIT of the 1,024 input coefficients; each of the block's 320
+// threads owns two of the 640 padded output words.  With SPLIT > 1 the SPLIT
+// blocks of a gate group add their partial sums into outputs zeroed first
+// (32-bit atomic adds: the order of the additions does not change the result).
+// Key rows read per gate: 3 x 8 x 1,024 x 2.5 KB / T.
 // ---------------------------------------------------------------------------
 constexpr int KS_THREADS = 320;
 
-template <int T>
+template <int T, int SPLIT>
 __global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict__ items, uint32_t count,
                                                          const uint32_t* __restrict__ ksk) {
-  __shared__ uint32_t s_a[T][RING_N];
+  constexpr int NI = RING_N / SPLIT;
+  __shared__ uint32_t s_a[T][NI];
   const uint32_t base = blockIdx.x * T;
+  const int i0 = blockIdx.y * NI;
   const int nt = (int)min((uint32_t)T, count - base);
-  for (int idx = threadIdx.x; idx < T * RING_N; idx += KS_THREADS) {
-    const int g = idx / RING_N, i = idx % RING_N;
+  for (int idx = threadIdx.x; idx < T * NI; idx += KS_THREADS) {
+    const int g = idx / NI, i = i0 + idx % NI;
     uint32_t a = 0;
     if (g < nt) {
       const KsItem& it = items[base + g];
       a = it.u1[i] + (it.u2 ? it.u2[i] : 0u);
     }
-    s_a[g][i] = a + (1u << 15);  // rounding offset of the key-switching digits
+    s_a[g][i - i0] = a + (1u << 15);  // rounding offset of the key-switching digits
   }
   const int w0 = threadIdx.x, w1 = threadIdx.x + KS_THREADS;
   uint32_t acc[T][2];
 #pragma unroll
   for (int g = 0; g < T; ++g) {
     uint32_t body = 0;
-    if (g < nt && w1 == LWE_n) {  // the body word sits in the second half (320 <= 630 < 640)
+    if (blockIdx.y == 0 && g < nt && w1 == LWE_n) {  // the body word sits in the second half (320 <= 630 < 640)
       const KsItem& it = items[base + g];
       body = it.u1[RING_N] + (it.u2 ? it.u2[RING_N] : 0u) + it.cst;
     }
@@ -590,10 +596,10 @@ __global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict
     acc[g][1] = body;
   }
   __syncthreads();
-  for (int i = 0; i < RING_N; ++i) {
+  for (int i = i0; i < i0 + NI; ++i) {
     uint32_t a[T];
 #pragma unroll
-    for (int g = 0; g < T; ++g) a[g] = s_a[g][i];
+    for (int g = 0; g < T; ++g) a[g] = s_a[g][i - i0];
 #pragma unroll 2
     for (int j = 0; j < KS_T; ++j) {
       const uint32_t* row = ksk + (size_t)((i * KS_T + j) * 3) * KS_ROW;
@@ -615,10 +621,22 @@ __global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict
   for (int g = 0; g < T; ++g) {
     if (g < nt) {
       uint32_t* out = items[base + g].out;
-      if (w0 < CT_n) out[w0] = acc[g][0];
-      if (w1 < CT_n) out[w1] = acc[g][1];
+      if (SPLIT == 1) {
+        if (w0 < CT_n) out[w0] = acc[g][0];
+        if (w1 < CT_n) out[w1] = acc[g][1];
+      } else {
+        if (w0 < CT_n) atomicAdd(out + w0, acc[g][0]);
+        if (w1 < CT_n) atomicAdd(out + w1, acc[g][1]);
+      }
     }
   }
+}
+
+// Zeroes the outputs of count key-switching items (before split key switching).
+__global__ void ks_zero_kernel(const KsItem* __restrict__ items, uint32_t count) {
+  const size_t total = (size_t)count * CT_n;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x)
+    items[k / CT_n].out[k % CT_n] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -789,15 +807,21 @@ int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_
 
 int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream) {
   if (count == 0) return 0;
+  const uint32_t groups = (count + gates_per_block - 1) / gates_per_block;
+  if (gates_per_block != 4) {
+    const size_t words = (size_t)count * CT_n;
+    const uint32_t zb = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(ks_zero_kernel, dim3(zb), dim3(256), 0, S(stream), items, count);
+  }
   switch (gates_per_block) {
     case 4:
-      hipLaunchKernelGGL(ks_kernel<4>, dim3((count + 3) / 4), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
+      hipLaunchKernelGGL((ks_kernel<4, 1>), dim3(groups), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
       break;
     case 8:
-      hipLaunchKernelGGL(ks_kernel<8>, dim3((count + 7) / 8), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
+      hipLaunchKernelGGL((ks_kernel<8, 2>), dim3(groups, 2), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
       break;
     case 16:
-      hipLaunchKernelGGL(ks_kernel<16>, dim3((count + 15) / 16), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
+      hipLaunchKernelGGL((ks_kernel<16, 4>), dim3(groups, 4), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
       break;
     default: return (int)hipErrorInvalidValue;
   }

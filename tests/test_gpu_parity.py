@@ -48,18 +48,30 @@ def test_bootstrap_parity(gpu, oracle_keys):
             assert np.array_equal(got[b], want[b]), (mu, b)
 
 
-def test_keyswitch_parity(gpu, oracle_keys):
+@pytest.mark.parametrize("gates_per_block", [4, 8, 16])
+def test_keyswitch_parity(gpu, oracle_keys, gates_per_block):
+    """Every key-switching workgroup shape (8 and 16 gates per workgroup split
+    the coefficients over 2 and 4 workgroups whose partial sums are added
+    atomically) equals the oracle; 21 gates leave a partial last group; the
+    outputs start dirty, so the zeroing before split sums is exercised."""
     vlp, ctx, ks = gpu
     B = 21
     ins = _rand_words(3, (B, O.N + 1))
     ins[0] = 0
     d_in = ctx.tensor(ins)
-    d_out = ctx.empty(B, O.n + 1)
-    vlp.vlp_keyswitch(ctx.ctx, ks, d_in, d_out, B)
-    ctx.sync()
+    d_out = ctx.tensor(_rand_words(4, (B, O.n + 1)))
+    old = vlp.vlp_get_tuning(ctx.ctx)
+    try:
+        vlp.vlp_set_tuning(ctx.ctx, old.br_rotations_per_block, old.br_blocks_per_cu, gates_per_block,
+                           old.br_waves_per_rotation)
+        vlp.vlp_keyswitch(ctx.ctx, ks, d_in, d_out, B)
+        ctx.sync()
+    finally:
+        vlp.vlp_set_tuning(ctx.ctx, old.br_rotations_per_block, old.br_blocks_per_cu, old.ks_gates_per_block,
+                           old.br_waves_per_rotation)
     got = ctx.to_host(d_out)
     for b in range(B):
-        assert np.array_equal(got[b], O.keyswitch(oracle_keys, ins[b])), b
+        assert np.array_equal(got[b], O.keyswitch(oracle_keys, ins[b])), (gates_per_block, b)
 
 
 @pytest.mark.parametrize("op", ["AND", "OR", "NAND", "XOR", "XNOR", "NOT", "MUX"])
