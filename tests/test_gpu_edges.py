@@ -1,0 +1,124 @@
+"""Edge cases through the C ABI: empty batches, argument errors, the memory
+budget, tuning validation, and the extreme shapes of the evaluation
+(64-bit identifiers, 2-bit intervals, one record, one payload bit)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import workloads as W
+from paper_2506_12761_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu(oracle_keys):
+    from paper_2506_12761_amd import vlp
+    ctx = vlp.Context(0)
+    ks = ctx.load_keys(oracle_keys.bk, oracle_keys.ksk)
+    yield vlp, ctx, ks
+    ctx.close()
+
+
+def _words(seed, shape):
+    return synth.uniform_u32(synth.stream(seed, "edge"), shape)
+
+
+def test_empty_batches_are_noops(gpu):
+    vlp, ctx, ks = gpu
+    a = ctx.tensor(_words(1, (2, O.n + 1)))
+    big = ctx.tensor(_words(2, (2, O.N + 1)))
+    before_a, before_big = ctx.to_host(a).copy(), ctx.to_host(big).copy()
+    vlp.vlp_bootstrap(ctx.ctx, ks, a, big, O.MU, 0)
+    vlp.vlp_keyswitch(ctx.ctx, ks, big, a, 0)
+    vlp.vlp_gate(ctx.ctx, ks, "AND", a, a, None, big, 0)
+    ctx.sync()
+    assert np.array_equal(ctx.to_host(a), before_a) and np.array_equal(ctx.to_host(big), before_big)
+
+
+def test_argument_errors(gpu):
+    vlp, ctx, ks = gpu
+    x = ctx.tensor(_words(3, (4, O.n + 1)))
+    y = ctx.tensor(_words(4, (4, O.n + 1)))
+
+    def einval(fn, *args):
+        with pytest.raises(vlp.VlpError) as e:
+            fn(*args)
+        assert e.value.status == vlp.VLP_EINVAL, e.value
+
+    einval(vlp.vlp_gate, ctx.ctx, ks, "AND", x, y, None, x[1:], 3)          # output overlaps an input
+    einval(vlp.vlp_gate, ctx.ctx, ks, "AND", x, None, None, y, 4)           # AND needs b
+    einval(vlp.vlp_gate, ctx.ctx, ks, "XOR", x, y, x, y[2:], 2)            # c only for MUX
+    einval(vlp.vlp_gate, ctx.ctx, ks, "MUX", x, y, None, y[2:], 2)         # MUX needs c
+    einval(vlp.vlp_gate, ctx.ctx, ks, 42, x, y, None, y, 1)                # unknown op
+    einval(vlp.vlp_keyswitch, ctx.ctx, ks, x, x, 1)                         # in and out overlap
+    einval(vlp.vlp_bootstrap, ctx.ctx, None, x, y, O.MU, 1)                 # no keyset
+    einval(vlp.vlp_evaluate, ctx.ctx, ks, vlp.make_shape("idm", 2, 4, 0, 1, True, 17), x, y, None, None, None)
+    einval(vlp.vlp_evaluate, ctx.ctx, ks, vlp.make_shape("intv", 2, 1, 0, 1), x, y, None, None, None)
+    # The failed calls left the context usable.
+    vlp.vlp_gate(ctx.ctx, ks, "NOT", x, None, None, y, 4)
+    ctx.sync()
+    assert np.array_equal(ctx.to_host(y), (0 - ctx.to_host(x).astype(np.uint64)).astype(np.uint32))
+
+
+def test_keyset_of_another_context_is_rejected(gpu, oracle_keys):
+    vlp, ctx, ks = gpu
+    other = vlp.Context(0)
+    try:
+        x = ctx.tensor(_words(5, (1, O.n + 1)))
+        y = ctx.empty(1, O.N + 1)
+        with pytest.raises(vlp.VlpError) as e:
+            vlp.vlp_bootstrap(other.ctx, ks, x, y, O.MU, 1)
+        assert e.value.status == vlp.VLP_EINVAL
+    finally:
+        other.close()
+
+
+def test_budget_too_small_for_a_keyset(oracle_keys):
+    from paper_2506_12761_amd import vlp
+    small = vlp.Context(0, hbm_budget=64 << 20)  # below the 124.8 MB a keyset needs
+    try:
+        used0, budget = vlp.vlp_mem_info(small.ctx)
+        assert budget == 64 << 20
+        with pytest.raises(vlp.VlpError) as e:
+            small.load_keys(oracle_keys.bk, oracle_keys.ksk)
+        assert e.value.status == vlp.VLP_EBUDGET
+        assert vlp.vlp_mem_info(small.ctx)[0] == used0
+    finally:
+        small.close()
+
+
+@pytest.mark.parametrize("bad", [(1, 1, 4, 3), (8, 1, 4, 2), (2, 1, 4, 4), (4, 0, 4, 0), (4, 65, 4, 0), (4, 1, 5, 0)])
+def test_tuning_validation(gpu, bad):
+    vlp, ctx, ks = gpu
+    old = vlp.vlp_get_tuning(ctx.ctx)
+    with pytest.raises(vlp.VlpError) as e:
+        vlp.vlp_set_tuning(ctx.ctx, *bad)
+    assert e.value.status == vlp.VLP_EINVAL
+    now = vlp.vlp_get_tuning(ctx.ctx)
+    assert (now.br_rotations_per_block, now.br_blocks_per_cu, now.ks_gates_per_block, now.br_waves_per_rotation) == \
+        (old.br_rotations_per_block, old.br_blocks_per_cu, old.ks_gates_per_block, old.br_waves_per_rotation)
+
+
+@pytest.mark.parametrize("mode,M,l,lS,d", [
+    ("idm", 2, 64, 1, 1),    # widest identifiers, one payload bit
+    ("intv", 3, 2, 2, 1),    # narrowest signed intervals
+    ("idm", 1, 5, 5, 1),     # one record: the result is the selection itself
+    ("cov", 1, 3, 0, 1),     # one record, one coordinate, no payload
+])
+def test_evaluate_extreme_shapes(gpu, oracle_keys, mode, M, l, lS, d):
+    vlp, ctx, ks = gpu
+    P = W.plain_workload(mode, M, l, lS, d, seed=500 + M * l)
+    enc = W.encrypt_workload(oracle_keys, P, seed=501 + l)
+    q, loc = ctx.tensor(enc["query"]), ctx.tensor(enc["db_loc"])
+    pay = ctx.tensor(enc["db_pay"]) if lS else None
+    R = ctx.empty(lS, O.n + 1) if lS else None
+    v = ctx.empty(M, O.n + 1)
+    vlp.vlp_evaluate(ctx.ctx, ks, vlp.make_shape(mode, M, l, lS, d), q, loc, pay, R, v)
+    ctx.sync()
+    v_want, R_want = W.oracle_outputs(oracle_keys, P, enc)
+    assert np.array_equal(ctx.to_host(v), v_want)
+    assert np.array_equal(O.decrypt(oracle_keys, ctx.to_host(v)), P["v"])
+    if lS:
+        assert np.array_equal(ctx.to_host(R), R_want)
+        assert np.array_equal(O.decrypt(oracle_keys, ctx.to_host(R)), P["R"])
