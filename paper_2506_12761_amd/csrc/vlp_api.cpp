@@ -146,12 +146,14 @@ bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
 int mark_begin(vlp_ctx* ctx);
 void mark_end(vlp_ctx* ctx, int id, int kind, uint64_t items);
 
-// Blind rotations are launched in chunks of one item per resident wavefront
-// (CUs x workgroups per CU x waves per workgroup).  Wavefronts that start
+// Blind rotations are launched in rounds that the device holds at once
+// (CUs x workgroups per CU x rotations per workgroup): rotations that start
 // together walk the key in step, so each key row reaches L2 once for many of
-// them; a persistent loop over many rounds lets them drift apart and
-// re-fetch the key (measured: ~0.5 MB vs up to ~36 MB of key traffic per
-// blind rotation).
+// them (a persistent loop over many rounds let them drift apart and re-fetch
+// the key: up to ~36 MB instead of ~0.5 MB of key traffic per rotation).
+// Automatic mode: a round of at most 2 rotations per CU runs on the
+// four-wavefront kernel (half the latency), larger rounds on the
+// two-wavefront kernel.
 int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
   const uint32_t mode = ctx->tune.br_waves_per_rotation, bpc = ctx->tune.br_blocks_per_cu;
   const uint32_t rpb = ctx->tune.br_rotations_per_block, cus = (uint32_t)ctx->num_cus;
@@ -242,7 +244,7 @@ uint32_t encode_bit(uint32_t bit) { return bit ? MU : 0u - MU; }
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
-extern "C" const char* vlp_version(void) { return "vlp 0.2 (gfx950, two-prime NTT)"; }
+extern "C" const char* vlp_version(void) { return "vlp 0.3 (gfx950, two-prime NTT)"; }
 
 extern "C" void vlp_default_params(vlp_params* p) {
   if (!p) return;
