@@ -235,7 +235,8 @@ def server_enc_bench(args):
 def serve_bench(args):
     """Poisson stream of PIR queries, modes uniform over {IntV 16-bit, CoV 20-bit,
     IdM 32-bit}, records log-uniform in [min, max], 64 payload bits, one of
-    `clients` key sets each; reports latency percentiles and queries/s."""
+    `clients` key sets each; reports latency percentiles (arrival to the
+    result R copied to the host) and queries/s."""
     import numpy as np
     import torch
 

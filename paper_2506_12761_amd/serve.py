@@ -57,6 +57,9 @@ class Executor:
     def destroy(self, handle) -> None:
         raise NotImplementedError
 
+    def fetch(self, req: "Request") -> None:  # copy a finished request's result to the host
+        pass
+
 
 class GpuExecutor(Executor):
     """libvlp programs on one device; keysets[client] must already be loaded."""
@@ -98,6 +101,10 @@ class GpuExecutor(Executor):
         self._left.pop(handle, None)
         self.vlp.vlp_program_destroy(self.ctx.ctx, handle)
 
+    def fetch(self, req):
+        R = req.payload.get("R")
+        req.payload["R_host"] = self.ctx.to_host(R).copy() if R is not None else None
+
 
 def serve(requests: list[Request], executor: Executor, max_active: int | None = None,
           clock=time.perf_counter, sleep=time.sleep, log=None) -> dict:
@@ -106,7 +113,8 @@ def serve(requests: list[Request], executor: Executor, max_active: int | None = 
     Arrival times are offsets from the start.  A request is admitted at the
     first step boundary after its arrival at which the executor accepts it
     (arrival order, no overtaking); each step advances every admitted,
-    unfinished request by one circuit level."""
+    unfinished request by one circuit level.  A request's latency runs from
+    its arrival to its result copied to the host."""
     pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
     waiting: list[Request] = []
     active: list[Request] = []
@@ -139,11 +147,11 @@ def serve(requests: list[Request], executor: Executor, max_active: int | None = 
         executor.step([r.handle for r in active])
         steps += 1
         max_active_seen = max(max_active_seen, len(active))
-        now = clock() - t0
         still = []
         for r in active:
             if executor.levels_left(r.handle) == 0:
-                r.finished = now
+                executor.fetch(r)  # the result on the host ends the request's latency
+                r.finished = clock() - t0
                 executor.destroy(r.handle)
                 r.handle = None
                 done.append(r)
