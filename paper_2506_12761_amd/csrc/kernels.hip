@@ -688,36 +688,54 @@ __device__ __forceinline__ uint32_t enc_word(const int64_t* vals, const uint8_t*
   return bit ? MU : 0u - MU;
 }
 
-// Out of place: four consecutive words per thread (16-byte accesses; pk and
-// out 16-byte aligned), the last words % 4 words by the first threads.  IDX is
-// the index type: 32-bit when the array has fewer than 2^32 words (cheaper
-// division by 631), else 64-bit.  The output is written with non-temporal
-// stores: it is not read again by this pass.
-template <typename IDX>
+// Out of place, 16-byte accesses (pk and out 16-byte aligned): each thread
+// issues U loads of four consecutive words (a block's U loads cover U
+// consecutive runs of blockDim quads) before it adds the body words and
+// stores, so U x 16 bytes per lane are in flight; the last words % 4 words
+// are done by the first threads.  IDX is the index type: 32-bit when the
+// array has fewer than 2^32 words (cheaper division by 631), else 64-bit.
+// Loads and stores are non-temporal: every word is touched once.
+__device__ __forceinline__ void add_body(uint4& w, uint32_t r, uint32_t e) {
+  switch (CT_n - 1 - r) {
+    case 0: w.x += e; break;
+    case 1: w.y += e; break;
+    case 2: w.z += e; break;
+    default: w.w += e; break;
+  }
+}
+
+template <typename IDX, int U>
 __global__ void server_enc_copy_kernel(const uint4* __restrict__ pk, uint4* __restrict__ out, size_t count,
                                        const int64_t* __restrict__ vals, const uint8_t* __restrict__ bytes,
                                        uint32_t l) {
   const IDX words = (IDX)(count * CT_n), quads = words / 4;
-  const IDX stride = (IDX)gridDim.x * blockDim.x;
-  for (IDX q = (IDX)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
-    uint4 w = pk[q];
-    const IDX w0 = 4 * q;
-    const IDX t = w0 / CT_n;
-    const uint32_t r = (uint32_t)(w0 - t * CT_n);  // word index of w.x inside ciphertext t
-    // The body word (CT_n - 1) is one of the four iff r >= CT_n - 4.
-    if (r >= CT_n - 4) {
-      const uint32_t e = enc_word(vals, bytes, l, t);
-      switch (CT_n - 1 - r) {
-        case 0: w.x += e; break;
-        case 1: w.y += e; break;
-        case 2: w.z += e; break;
-        default: w.w += e; break;
+  const IDX stride = (IDX)gridDim.x * blockDim.x * U;
+  for (IDX q0 = (IDX)blockIdx.x * blockDim.x * U + threadIdx.x; q0 < quads; q0 += stride) {
+    uint4 w[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const IDX q = q0 + (IDX)k * blockDim.x;
+      if (q < quads) {
+        w[k].x = __builtin_nontemporal_load(&pk[q].x);
+        w[k].y = __builtin_nontemporal_load(&pk[q].y);
+        w[k].z = __builtin_nontemporal_load(&pk[q].z);
+        w[k].w = __builtin_nontemporal_load(&pk[q].w);
       }
     }
-    __builtin_nontemporal_store(w.x, &out[q].x);
-    __builtin_nontemporal_store(w.y, &out[q].y);
-    __builtin_nontemporal_store(w.z, &out[q].z);
-    __builtin_nontemporal_store(w.w, &out[q].w);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const IDX q = q0 + (IDX)k * blockDim.x;
+      if (q < quads) {
+        const IDX w0 = 4 * q;
+        const IDX t = w0 / CT_n;
+        const uint32_t r = (uint32_t)(w0 - t * CT_n);  // word index of w.x inside ciphertext t
+        if (r >= CT_n - 4) add_body(w[k], r, enc_word(vals, bytes, l, t));  // the body word is one of the four
+        __builtin_nontemporal_store(w[k].x, &out[q].x);
+        __builtin_nontemporal_store(w[k].y, &out[q].y);
+        __builtin_nontemporal_store(w[k].z, &out[q].z);
+        __builtin_nontemporal_store(w[k].w, &out[q].w);
+      }
+    }
   }
   const IDX tid = (IDX)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid < words - 4 * quads) {
@@ -859,15 +877,15 @@ int launch_server_enc(const uint32_t* pk, uint32_t* out, size_t count, const int
     hipLaunchKernelGGL(server_enc_inplace_kernel, dim3((uint32_t)blocks), dim3(256), 0, S(stream), out, count, vals,
                        bytes, l);
   } else if ((((uintptr_t)pk | (uintptr_t)out) & 15) == 0) {
-    // Enough threads for the word tail (< 4) in the first block; 16 waves per CU
-    // in flight, grid-stride beyond that.
+    // At most 4,096 workgroups (more than the device holds at once), grid-stride
+    // beyond that; the first workgroup also covers the word tail (< 4 words).
     const size_t quads = words / 4;
     const size_t blocks = std::max<size_t>(1, std::min<size_t>((quads + 255) / 256, 4096));
     if (words < (1ull << 32))
-      hipLaunchKernelGGL(server_enc_copy_kernel<uint32_t>, dim3((uint32_t)blocks), dim3(256), 0, S(stream),
+      hipLaunchKernelGGL((server_enc_copy_kernel<uint32_t, 4>), dim3((uint32_t)blocks), dim3(256), 0, S(stream),
                          reinterpret_cast<const uint4*>(pk), reinterpret_cast<uint4*>(out), count, vals, bytes, l);
     else
-      hipLaunchKernelGGL(server_enc_copy_kernel<uint64_t>, dim3((uint32_t)blocks), dim3(256), 0, S(stream),
+      hipLaunchKernelGGL((server_enc_copy_kernel<uint64_t, 4>), dim3((uint32_t)blocks), dim3(256), 0, S(stream),
                          reinterpret_cast<const uint4*>(pk), reinterpret_cast<uint4*>(out), count, vals, bytes, l);
   } else {
     const size_t blocks = std::min<size_t>((words + 255) / 256, 8192);
