@@ -66,7 +66,8 @@ int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_
                void* stream);
 // Four wavefronts per rotation (prime x accumulator half), one rotation per workgroup.
 int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream);
-int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream);
+int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block,
+                    uint32_t min_blocks, void* stream);
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
                          uint32_t cst, uint32_t mu, uint32_t* out, const uint32_t* bk, void* stream);
 int launch_make_ks_items(KsItem* items, uint32_t count, const uint32_t* u1, const uint32_t* u2, uint32_t cst,

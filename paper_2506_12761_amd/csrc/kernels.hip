@@ -823,15 +823,25 @@ int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_
   return (int)hipGetLastError();
 }
 
-int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block, void* stream) {
+int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block,
+                    uint32_t min_blocks, void* stream) {
   if (count == 0) return 0;
-  const uint32_t groups = (count + gates_per_block - 1) / gates_per_block;
-  if (gates_per_block != 4) {
+  // Launches too small to fill the device (fewer than min_blocks workgroups)
+  // split the coefficients 8 ways instead: 8x the workgroups, each walking an
+  // eighth of the key rows, which cuts the latency of a small launch.
+  const bool small = (count + gates_per_block - 1) / gates_per_block < min_blocks;
+  const uint32_t T = small ? 4 : gates_per_block;
+  const uint32_t groups = (count + T - 1) / T;
+  if (small || T != 4) {
     const size_t words = (size_t)count * CT_n;
     const uint32_t zb = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
     hipLaunchKernelGGL(ks_zero_kernel, dim3(zb), dim3(256), 0, S(stream), items, count);
   }
-  switch (gates_per_block) {
+  if (small) {
+    hipLaunchKernelGGL((ks_kernel<4, 8>), dim3(groups, 8), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
+    return (int)hipGetLastError();
+  }
+  switch (T) {
     case 4:
       hipLaunchKernelGGL((ks_kernel<4, 1>), dim3(groups), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
       break;

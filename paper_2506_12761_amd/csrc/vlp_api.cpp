@@ -186,7 +186,8 @@ int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
 int timed_ks(vlp_ctx* ctx, const KsItem* items, uint32_t count, const uint32_t* ksk) {
   if (count == 0) return 0;
   const int m = mark_begin(ctx);
-  const int e = launch_ks_group(items, count, ksk, ctx->tune.ks_gates_per_block, ctx->stream);
+  const int e = launch_ks_group(items, count, ksk, ctx->tune.ks_gates_per_block, (uint32_t)ctx->num_cus * 2,
+                                ctx->stream);
   mark_end(ctx, m, 1, count);
   return e;
 }
