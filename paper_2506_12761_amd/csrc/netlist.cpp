@@ -12,6 +12,7 @@
 #include "netlist.h"
 
 #include <algorithm>
+#include <cstring>
 
 namespace vlp {
 
@@ -126,9 +127,15 @@ std::vector<Operand> bits(Operand (*mk)(uint32_t), uint32_t base, uint32_t l) {
 
 }  // namespace
 
+static_assert(sizeof(vlp_mode) == sizeof(int), "the mode field is read as an int");
+
 bool shape_valid(const vlp_shape& sh, const char** why) {
   const uint32_t M = sh.M, l = sh.l_I, lS = sh.l_S, d = sh.d;
-  if (sh.mode != VLP_INTV && sh.mode != VLP_COV && sh.mode != VLP_IDM) { *why = "unknown mode"; return false; }
+  // A C caller may store any integer in the mode field: read its bytes as an
+  // int (loading an enum outside its enumerators is undefined in C++).
+  int mode;
+  std::memcpy(&mode, &sh.mode, sizeof mode);
+  if (mode != VLP_INTV && mode != VLP_COV && mode != VLP_IDM) { *why = "unknown mode"; return false; }
   if (M == 0 || M > (1u << 24)) { *why = "M must be in [1, 2^24]"; return false; }
   if (l < 1 || l > 64) { *why = "l_I must be in [1, 64]"; return false; }
   if (sh.mode == VLP_INTV && l < 2) { *why = "IntV needs l_I >= 2"; return false; }
@@ -140,9 +147,9 @@ bool shape_valid(const vlp_shape& sh, const char** why) {
 
 bool build_netlist(const vlp_shape& sh, Netlist& nl, const char** why) {
   nl = Netlist();
+  if (!shape_valid(sh, why)) return false;
   const uint32_t M = sh.M, l = sh.l_I, lS = sh.l_S;
   const uint32_t d = sh.mode == VLP_IDM ? 1 : sh.d;
-  if (!shape_valid(sh, why)) return false;
   nl.M = M;
   nl.l_S = lS;
   Builder B{nl};
