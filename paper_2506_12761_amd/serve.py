@@ -33,8 +33,10 @@ class Request:
     d: int
     arrival: float                # seconds since the start of the run
     payload: dict = field(default_factory=dict)  # executor-specific buffers
+    cancel_at: float | None = None  # the client withdraws the query at this offset, if not done by then
     admitted: float | None = None
     finished: float | None = None
+    cancelled: float | None = None  # when the server dropped it after cancellation
     handle: object = None
 
     @property
@@ -114,11 +116,15 @@ def serve(requests: list[Request], executor: Executor, max_active: int | None = 
     first step boundary after its arrival at which the executor accepts it
     (arrival order, no overtaking); each step advances every admitted,
     unfinished request by one circuit level.  A request's latency runs from
-    its arrival to its result copied to the host."""
+    its arrival to its result copied to the host.  A request whose cancel_at
+    has passed is dropped at the next step boundary: never admitted if still
+    queued, otherwise its program is destroyed and its memory freed for the
+    queue."""
     pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
     waiting: list[Request] = []
     active: list[Request] = []
     done: list[Request] = []
+    dropped: list[Request] = []
     t0 = clock()
     steps = 0
     max_active_seen = 0
@@ -127,6 +133,19 @@ def serve(requests: list[Request], executor: Executor, max_active: int | None = 
         now = clock() - t0
         while pending and pending[0].arrival <= now:
             waiting.append(pending.pop(0))
+        # Cancellations: queued requests leave the queue, running ones free their memory.
+        gone = [r for r in waiting + active if r.cancel_at is not None and r.cancel_at <= now]
+        for r in gone:
+            if r.handle is not None:
+                executor.destroy(r.handle)
+                r.handle = None
+            r.cancelled = now
+            dropped.append(r)
+        if gone:
+            waiting = [r for r in waiting if r.cancelled is None]
+            active = [r for r in active if r.cancelled is None]
+            if not (pending or waiting or active):
+                break
         # Admission in arrival order while memory allows.
         while waiting and (max_active is None or len(active) < max_active):
             r = waiting[0]
@@ -172,6 +191,7 @@ def serve(requests: list[Request], executor: Executor, max_active: int | None = 
         "steps": steps,
         "max_active": max_active_seen,
         "budget_rejections": rejected_attempts,
+        "cancelled": len(dropped),
         "requests": done,
     }
 

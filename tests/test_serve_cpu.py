@@ -99,3 +99,29 @@ def test_idle_gaps_advance_to_next_arrival():
     st = serve(_reqs([("cov", 10, 0.0), ("cov", 10, 5.0)]), ex, clock=clk, sleep=clk.sleep)
     lat = sorted(r.latency for r in st["requests"])
     assert all(abs(x - 0.7) < 1e-9 for x in lat)
+
+
+def test_cancellation_frees_memory_for_the_queue():
+    """A running request cancelled by its client releases its memory at the
+    next step, so a queued one is admitted before the first would have ended;
+    a request cancelled while queued is never admitted."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk, budget=100)
+    reqs = _reqs([("idm", 90, 0.0), ("cov", 80, 0.05), ("intv", 10, 0.06)])
+    reqs[0].cancel_at = 0.35          # running, 23 levels: cancelled after a few steps
+    reqs[2].cancel_at = 0.07          # queued behind the second: cancelled before admission
+    st = serve(reqs, ex, clock=clk, sleep=clk.sleep)
+    assert st["cancelled"] == 2 and st["queries"] == 1
+    assert reqs[0].cancelled is not None and reqs[0].finished is None
+    assert reqs[2].admitted is None and reqs[2].cancelled is not None
+    assert reqs[1].finished is not None and reqs[1].admitted <= 0.45  # admitted once the first was dropped
+    assert ex.used == 0 and not ex.left
+
+
+def test_cancel_after_finish_is_a_noop():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, budget=100)
+    reqs = _reqs([("cov", 10, 0.0)])
+    reqs[0].cancel_at = 50.0
+    st = serve(reqs, ex, clock=clk, sleep=clk.sleep)
+    assert st["queries"] == 1 and st["cancelled"] == 0 and reqs[0].cancelled is None
