@@ -477,6 +477,13 @@ def main():
                                4: "br4_kernel"}[launch["br_waves_per_rotation"]],
                     "launches": br["launches"], "avg_launch_ms": avg_ms,
                     "ks_kernel_ms_share": prof["ks"]["ms"] / max(1e-9, prof["ks"]["ms"] + br["ms"])}
+        # Beside the derived peak: the measured rate of the transforms' own butterflies
+        # (register-resident, every CU busy, the 6:2 forward:inverse mix of a CMux).
+        mp = vlp.vlp_measure_modmul_peak(0)
+        roofline["peak_measured"] = mp["mixed"] / 1e12
+        roofline["frac_of_peak_measured"] = achieved / mp["mixed"]
+        log("measured butterfly peak: %.3f T/s forward, %.3f T/s inverse, %.3f T/s mixed"
+            % (mp["fwd"] / 1e12, mp["inv"] / 1e12, mp["mixed"] / 1e12))
 
     cpu = None
     if not args.no_cpu_baseline:

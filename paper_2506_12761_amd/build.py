@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvlp.so")
-SOURCES = ["kernels.hip", "vlp_api.cpp", "netlist.cpp", "twiddles.cpp"]
+SOURCES = ["kernels.hip", "peak.hip", "vlp_api.cpp", "netlist.cpp", "twiddles.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t
     uint32_t* dst = bk_ntt + (size_t)poly * 2 * RING_N;  // plane of P1, then plane of P2
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const uint32_t a = csub(csub(v.a[r], 2 * P1), P1), b = csub(csub(v.b[r], 2 * P2), P2);
+      const uint32_t a = v.a[r] % P1, b = v.b[r] % P2;  // lazy forward output (< 22P), once per key
       dst[r * 64 + lane] = csub(shoup(a, scale.x, scale.y, P1), P1);
       dst[RING_N + r * 64 + lane] = csub(shoup(b, scale.z, scale.w, P2), P2);
     }
@@ -119,10 +119,11 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
       if (ab == 0) continue;
       // External product BK_i x (X^ab acc - acc): the six digit polynomials are
       // transformed one at a time and multiplied into the accumulators.
-      //  - wide (64-bit) accumulators take canonical residues: six products stay
-      //    below P * 2^32, the input range of one Montgomery reduction at the end;
-      //  - narrow (32-bit) accumulators reduce each product to [0, P) and sum
-      //    lazily (six terms < 6P < 2^32).
+      //  - wide (64-bit) accumulators take the lazy transform values (< 22P):
+      //    six products stay below 4P * 2^32, the input range of one Montgomery
+      //    reduction to [0, 4P) at the end;
+      //  - narrow (32-bit) accumulators reduce each product (< 22P^2 < P * 2^32)
+      //    to [0, P) and sum lazily (six terms < 6P < 2^32).
       Acc m0a[16], m0b[16], m1a[16], m1b[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) m0a[r] = m0b[r] = m1a[r] = m1b[r] = 0;
@@ -180,13 +181,13 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
               b1b[r] = k0[3 * RING_N + r * 64 + lane];
             }
             if constexpr (kWideAcc) {
-              const uint32_t da = csub(csub(v.a[r], 2 * P1), P1), db = csub(csub(v.b[r], 2 * P2), P2);  // [0, P)
+              const uint32_t da = v.a[r], db = v.b[r];  // [0, 22P)
               m0a[r] += (uint64_t)da * b0a[r];
               m0b[r] += (uint64_t)db * b0b[r];
               m1a[r] += (uint64_t)da * b1a[r];
               m1b[r] += (uint64_t)db * b1b[r];
             } else {
-              const uint32_t da = csub(v.a[r], 2 * P1), db = csub(v.b[r], 2 * P2);  // [0, 2P)
+              const uint32_t da = v.a[r], db = v.b[r];  // [0, 22P)
               m0a[r] += redc((uint64_t)da * b0a[r], P1, P1_INV);
               m0b[r] += redc((uint64_t)db * b0b[r], P2, P2_INV);
               m1a[r] += redc((uint64_t)da * b1a[r], P1, P1_INV);
@@ -200,9 +201,9 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
         Poly2 v;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          if constexpr (kWideAcc) {
-            v.a[r] = redc(c ? m1a[r] : m0a[r], P1, P1_INV);
-            v.b[r] = redc(c ? m1b[r] : m0b[r], P2, P2_INV);
+          if constexpr (kWideAcc) {  // [0, 4P) -> [0, 2P)
+            v.a[r] = csub(redc(c ? m1a[r] : m0a[r], P1, P1_INV), 2 * P1);
+            v.b[r] = csub(redc(c ? m1b[r] : m0b[r], P2, P2_INV), 2 * P2);
           } else {  // [0, 6P) -> [0, 2P)
             v.a[r] = csub(csub(c ? m1a[r] : m0a[r], 4 * P1), 2 * P1);
             v.b[r] = csub(csub(c ? m1b[r] : m0b[r], 4 * P2), 2 * P2);
@@ -251,7 +252,7 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
     if (SKIP && ab == 0) continue;  // the same decision in both wavefronts: abar is shared
     // 64-bit accumulators of the two output polynomials mod P: six products of
-    // transform values (< 4P) and key residues (< P) stay below 4P * 2^32, so
+    // transform values (< 22P) and key residues (< P) stay below 4P * 2^32, so
     // one reduction at the end gives [0, 4P) and a conditional subtract [0, 2P).
     uint64_t m0[16], m1[16];
 #pragma unroll
@@ -284,8 +285,8 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
           b1[r] = k0[2 * RING_N + r * 64 + lane];
         }
         const int shift = 32 - BG_BIT * (lev + 1);
-        // Balanced digit d in [-64, 63] as d + P in [P - 64, P + 63] (< 2P: the
-        // first stage takes inputs below 2P).
+        // Balanced digit d in [-64, 63] as d + P in [P - 64, P + 63]: below 2P,
+        // the input bound the forward transform's ranges start from.
         uint32_t x[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = ((D[r] >> shift) & 127u) + (P - 64);
@@ -420,8 +421,8 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
     const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
     if (ab == 0) continue;  // the same decision in all four wavefronts: abar is shared
-    // Three products of transform values (< 4P) and key residues (< P) per
-    // output: below 12 P^2 < 2P * 2^32, so one reduction gives [0, 2P).
+    // Three products of transform values (< 22P) and key residues (< P) per
+    // output: below 66 P^2 < 2P * 2^32, so one reduction gives [0, 2P).
     uint64_t m0[16], m1[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;

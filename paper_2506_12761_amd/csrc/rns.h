@@ -3,23 +3,27 @@
 // The blind rotation's polynomial products are integers of magnitude
 // < 6 * 1024 * 64 * 2^32 < 2^50.6 (6 digit polynomials with |digit| <= 64
 // times key words < 2^32, 1024 terms each).  They are computed modulo
-// Q = P1 * P2 (~2^58.8) with two NTT primes P_i = 1 (mod 2048) and lifted
-// back exactly: Q/2 > 2^57 exceeds every |coefficient|, so the centred
+// Q = P1 * P2 (~2^53.9) with two NTT primes P_i = 1 (mod 2048) and lifted
+// back exactly: Q/2 > 2^52.9 exceeds every |coefficient|, so the centred
 // residue is the integer itself and its low 32 bits are the torus result.
 //
-// Both primes are below 2^32 / 6 so that
-//   - lazy transform values stay in [0, 4P) < 2^32 (Harvey butterflies with
-//     Shoup twiddles: no 64-bit compares, only min() for conditional subtracts),
-//   - six products of canonical residues sum below P * 2^32, the input range
-//     of one Montgomery reduction (one reduction per accumulated coefficient).
+// Both primes are below 2^32 / 33 so that
+//   - the forward transform never reduces: a Cooley-Tukey butterfly with a
+//     Shoup twiddle (product in [0, 2P)) raises the bound of its values by 2P,
+//     so inputs below 2P leave the ten stages below 22P < 2^32;
+//   - six products of such values and canonical key residues sum below
+//     132 P^2 < 4P * 2^32, the input range of one Montgomery reduction to
+//     [0, 4P) (one reduction per accumulated coefficient);
+//   - the inverse transform's values stay in [0, 2P) with one conditional
+//     subtract per butterfly (unsigned min).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace vlp {
 
-constexpr uint32_t P1 = 715825153u;  // 0x2aaaa001 = 349524 * 2^11 + 1
-constexpr uint32_t P2 = 715804673u;  // 0x2aaa5001 = 349514 * 2^11 + 1
+constexpr uint32_t P1 = 130121729u;  // 0x07c18001 = 63536 * 2^11 + 1
+constexpr uint32_t P2 = 130103297u;  // 0x07c13801 = 63527 * 2^11 + 1
 
 // p^-1 mod 2^32 by Newton iteration (p odd).
 constexpr uint32_t inv_mod_2_32(uint32_t p) {
@@ -44,7 +48,7 @@ constexpr uint32_t C12 = (uint32_t)pow_mod(P1 % P2, P2 - 2, P2);
 constexpr uint32_t C12_SHOUP = (uint32_t)(((uint64_t)C12 << 32) / P2);
 constexpr uint64_t Q = (uint64_t)P1 * P2;
 
-static_assert(6ull * P1 < (1ull << 32) && 6ull * P2 < (1ull << 32), "primes too large for lazy ranges");
+static_assert(33ull * P1 < (1ull << 32) && 33ull * P2 < (1ull << 32), "primes too large for lazy ranges");
 static_assert((P1 - 1) % 2048 == 0 && (P2 - 1) % 2048 == 0, "primes need 2048-th roots of unity");
 static_assert(Q / 2 > (6ull * 1024 * 64) << 32, "modulus too small for an exact lift");
 static_assert(P1 < 2 * P2, "CRT difference range");
@@ -66,12 +70,15 @@ __device__ __forceinline__ uint32_t redc(uint64_t T, uint32_t p, uint32_t pinv) 
   return min(t, t + p);                                      // t < 0 wraps high; t + p is then in [0, p)
 }
 
-// Six products of a lazy transform value (< 4p) and a canonical key residue
-// (< p) sum below 24 p^2 < 2^64, whose high word stays below 4p: the
-// accumulators need no reduction of the transform output.
-static_assert((unsigned __int128)24 * P1 * P1 < ((unsigned __int128)1 << 64) &&
-                  (unsigned __int128)24 * P1 * P1 < ((unsigned __int128)4 * P1 << 32) &&
-                  (unsigned __int128)24 * P2 * P2 < ((unsigned __int128)4 * P2 << 32),
+// Six products of a lazy forward-transform value (< 22p) and a canonical key
+// residue (< p) sum below 132 p^2 < 4p * 2^32 (< 2^64): one reduction to
+// [0, 4p) and no reduction of the transform output.  Three such products
+// (one half of an output, the four-wavefront kernel) stay below 66 p^2 <
+// 2p * 2^32: one reduction to [0, 2p).
+static_assert((unsigned __int128)132 * P1 * P1 < ((unsigned __int128)4 * P1 << 32) &&
+                  (unsigned __int128)132 * P2 * P2 < ((unsigned __int128)4 * P2 << 32) &&
+                  (unsigned __int128)66 * P1 * P1 < ((unsigned __int128)2 * P1 << 32) &&
+                  (unsigned __int128)66 * P2 * P2 < ((unsigned __int128)2 * P2 << 32),
               "accumulator range");
 
 // Low 32 bits of the centred lift of (x1 mod P1, x2 mod P2), canonical inputs.

@@ -11,8 +11,10 @@
 // It reads the forward table too: psi^-brv10(2^s + i) = -psi^brv10(2^(s+1) - 1 - i),
 // so its stage s uses entry 2^(s+1) - 1 - i with the subtraction reversed.
 //
-// Butterflies are lazy (Harvey): forward values stay in [0, 4P), inverse in
-// [0, 2P); twiddles carry their Shoup quotient floor(w 2^32 / P).
+// Butterflies are lazy (Harvey): the forward transform never reduces (each
+// stage raises the bound by 2P: inputs below 2P end below 22P, which the
+// primes keep below 2^32), the inverse keeps its values in [0, 2P); twiddles
+// carry their Shoup quotient floor(w 2^32 / P).
 //
 // Three register layouts keep every butterfly inside a lane; two LDS
 // transposes per transform move between them:
@@ -64,11 +66,10 @@ __device__ __forceinline__ void wave_transpose(Poly2& v, uint2* buf, int lane) {
   }
 }
 
-// Cooley-Tukey: (x, y) -> (x + w y, x - w y); in and out in [0, 4P).  With
-// CANON the input x is known to be < 2P already (first stage: digit residues).
-template <bool CANON = false>
+// Cooley-Tukey: (x, y) -> (x + w y, x - w y) with w y taken in [0, 2P): for
+// x below B (any y) both outputs are below B + 2P.  No reduction.
 __device__ __forceinline__ void bfly_ct(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp, uint32_t p) {
-  const uint32_t u = CANON ? x : csub(x, 2 * p);
+  const uint32_t u = x;
   const uint32_t t = shoup(y, w, wp, p);
   x = u + t;
   y = u - t + 2 * p;
@@ -97,8 +98,8 @@ __device__ __forceinline__ void fwd_stage(Poly2& v, const Tw* tw, int lane) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int r = bfly_reg<RB>(k);
-    bfly_ct<S == 0>(v.a[r], v.a[r | (1 << RB)], w[k].x, w[k].y, P1);
-    bfly_ct<S == 0>(v.b[r], v.b[r | (1 << RB)], w[k].z, w[k].w, P2);
+    bfly_ct(v.a[r], v.a[r | (1 << RB)], w[k].x, w[k].y, P1);
+    bfly_ct(v.b[r], v.b[r | (1 << RB)], w[k].z, w[k].w, P2);
   }
 }
 template <int S, int (*LAY)(int, int), int RB>
@@ -115,7 +116,7 @@ __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
   }
 }
 
-// Forward: layout A (coefficient order, canonical values < P) -> layout C (transform order, < 4P).
+// Forward: layout A (coefficient order, values < 2P) -> layout C (transform order, < 22P).
 // Stages 0..3 use wavefront-uniform twiddles (their index depends only on the
 // register), read through `gtw` (the table in global memory: scalar loads into
 // SGPRs); the other stages read the LDS copy `tw` per lane.
@@ -211,7 +212,7 @@ __device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tws, 
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int r = bfly_reg<RB>(k);
-    bfly_ct<S == 0>(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
+    bfly_ct(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
   }
 }
 template <int PR, int S, int (*LAY)(int, int), int RB>

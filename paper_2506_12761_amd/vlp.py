@@ -32,7 +32,7 @@ EXPORTS = [
     "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_evaluate", "vlp_server_encrypt",
     "vlp_program_create", "vlp_program_reset", "vlp_step", "vlp_program_run", "vlp_program_counts",
     "vlp_plan_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
-    "vlp_profile_enable", "vlp_profile_read",
+    "vlp_profile_enable", "vlp_profile_read", "vlp_measure_modmul_peak",
 ]
 
 
@@ -99,6 +99,8 @@ def lib():
             "vlp_sync": (ctypes.c_int, [vp]),
             "vlp_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
             "vlp_profile_read": (ctypes.c_int, [vp, P(vlp_kernel_stats), P(vlp_kernel_stats)]),
+            "vlp_measure_modmul_peak": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double),
+                                                       P(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -268,6 +270,15 @@ def vlp_profile_read(ctx) -> dict:
     _check(ctx, lib().vlp_profile_read(ctx, ctypes.byref(br), ctypes.byref(ks)))
     return {"br": {"launches": br.launches, "items": br.items, "ms": br.ms},
             "ks": {"launches": ks.launches, "items": ks.items, "ms": ks.ms}}
+
+
+def vlp_measure_modmul_peak(device: int = 0) -> dict:
+    """Measured butterfly rates of `device` (modular multiplications per second)."""
+    f, i, m = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = lib().vlp_measure_modmul_peak(device, ctypes.byref(f), ctypes.byref(i), ctypes.byref(m))
+    if st != VLP_OK:
+        raise VlpError(st, "vlp_measure_modmul_peak failed")
+    return {"fwd": f.value, "inv": i.value, "mixed": m.value}
 
 
 # ---------------------------------------------------------------------------

@@ -106,3 +106,10 @@ def test_plan_rejects_bad_shapes():
                vlp.make_shape("idm", 4, 65)):
         with pytest.raises(vlp.VlpError):
             vlp.vlp_plan_counts(sh)
+
+
+def test_measure_peak_rejects_null_outputs():
+    """Argument checks come before any HIP call (no GPU needed)."""
+    L = vlp.lib()
+    d = ctypes.c_double()
+    assert L.vlp_measure_modmul_peak(0, None, ctypes.byref(d), ctypes.byref(d)) == vlp.VLP_EINVAL
