@@ -201,12 +201,12 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
         Poly2 v;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          if constexpr (kWideAcc) {  // [0, 4P) -> [0, 2P)
-            v.a[r] = csub(redc(c ? m1a[r] : m0a[r], P1, P1_INV), 2 * P1);
-            v.b[r] = csub(redc(c ? m1b[r] : m0b[r], P2, P2_INV), 2 * P2);
-          } else {  // [0, 6P) -> [0, 2P)
-            v.a[r] = csub(csub(c ? m1a[r] : m0a[r], 4 * P1), 2 * P1);
-            v.b[r] = csub(csub(c ? m1b[r] : m0b[r], 4 * P2), 2 * P2);
+          if constexpr (kWideAcc) {  // [0, 4P), the inverse transform's input range
+            v.a[r] = redc(c ? m1a[r] : m0a[r], P1, P1_INV);
+            v.b[r] = redc(c ? m1b[r] : m0b[r], P2, P2_INV);
+          } else {  // [0, 6P) -> [0, 4P)
+            v.a[r] = csub(c ? m1a[r] : m0a[r], 4 * P1);
+            v.b[r] = csub(c ? m1b[r] : m0b[r], 4 * P2);
           }
         }
         ntt_inv(v, buf, s_tw, tw_fwd, lane);
@@ -253,7 +253,7 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     if (SKIP && ab == 0) continue;  // the same decision in both wavefronts: abar is shared
     // 64-bit accumulators of the two output polynomials mod P: six products of
     // transform values (< 22P) and key residues (< P) stay below 4P * 2^32, so
-    // one reduction at the end gives [0, 4P) and a conditional subtract [0, 2P).
+    // one reduction at the end gives [0, 4P), the inverse transform's input range.
     uint64_t m0[16], m1[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;
@@ -304,12 +304,12 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     constexpr int KEEP = PR;
     uint32_t keep[16], x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = csub(redc(KEEP ? m1[r] : m0[r], P, PINV), 2 * P);
+    for (int r = 0; r < 16; ++r) x[r] = redc(KEEP ? m1[r] : m0[r], P, PINV);
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       keep[r] = csub(x[r], P);
-      x[r] = csub(redc(KEEP ? m0[r] : m1[r], P, PINV), 2 * P);
+      x[r] = redc(KEEP ? m0[r] : m1[r], P, PINV);
     }
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
     wave_lds_sync();  // the transform's last reads of buf are done
@@ -475,7 +475,7 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
     for (int r = 0; r < 16; ++r) oth[r] = half_partner_xbuf[r * 64 + lane];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = csub(x[r] + oth[r], 2 * P);  // [0, 2P)
+    for (int r = 0; r < 16; ++r) x[r] += oth[r];  // [0, 4P)
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
     // Wave (0, H) lifts registers 0..7, wave (1, H) registers 8..15: each parks
     // the half the other one lifts.

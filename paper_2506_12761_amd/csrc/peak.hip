@@ -24,8 +24,7 @@ constexpr int PEAK_ITERS = 2048;
 constexpr int BFLY_PER_ITER = 4 * 8;   // four stages (register strides 8, 4, 2, 1) of 8 butterflies
 
 // One lane's 16 residues, transformed over and over by the stages a
-// transform runs inside a lane.  Forward butterflies keep values in [0, 4P)
-// and inverse ones in [0, 2P), so both loops stay in range indefinitely.
+// transform runs inside a lane.
 template <bool INV>
 __global__ __launch_bounds__(PEAK_THREADS) void butterfly_peak_kernel(uint32_t* out, uint32_t seed, int iters) {
   constexpr uint32_t p = Prime<0>::P;
@@ -42,25 +41,30 @@ __global__ __launch_bounds__(PEAK_THREADS) void butterfly_peak_kernel(uint32_t* 
     asm volatile("" : "+v"(w[k]), "+v"(wp[k]));
   }
   for (int i = 0; i < iters; ++i) {
+    // Forward: the transform's butterflies never reduce, so over the loop's
+    // thousands of stages the values leave the residue ranges and wrap
+    // modulo 2^32; the instructions, and so their timing, do not depend on
+    // the values.  Inverse: sums double the bound three times (2P -> 16P) and
+    // the fourth stage reduces them, the pattern of the inverse transform.
 #pragma unroll
     for (int k = 0; k < 8; ++k) {  // register stride 8
       const int r = bfly_reg<3>(k);
-      if (INV) bfly_gs_neg(x[r], x[r | 8], w[k], wp[k], p); else bfly_ct(x[r], x[r | 8], w[k], wp[k], p);
+      if (INV) bfly_gs_neg<2, false>(x[r], x[r | 8], w[k], wp[k], p); else bfly_ct(x[r], x[r | 8], w[k], wp[k], p);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {  // stride 4
       const int r = bfly_reg<2>(k);
-      if (INV) bfly_gs_neg(x[r], x[r | 4], w[k], wp[k], p); else bfly_ct(x[r], x[r | 4], w[k], wp[k], p);
+      if (INV) bfly_gs_neg<4, false>(x[r], x[r | 4], w[k], wp[k], p); else bfly_ct(x[r], x[r | 4], w[k], wp[k], p);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {  // stride 2
       const int r = bfly_reg<1>(k);
-      if (INV) bfly_gs_neg(x[r], x[r | 2], w[k], wp[k], p); else bfly_ct(x[r], x[r | 2], w[k], wp[k], p);
+      if (INV) bfly_gs_neg<8, false>(x[r], x[r | 2], w[k], wp[k], p); else bfly_ct(x[r], x[r | 2], w[k], wp[k], p);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {  // stride 1
       const int r = bfly_reg<0>(k);
-      if (INV) bfly_gs_neg(x[r], x[r | 1], w[k], wp[k], p); else bfly_ct(x[r], x[r | 1], w[k], wp[k], p);
+      if (INV) bfly_gs_neg<16, true>(x[r], x[r | 1], w[k], wp[k], p); else bfly_ct(x[r], x[r | 1], w[k], wp[k], p);
     }
   }
   uint32_t s = 0;

@@ -14,8 +14,10 @@
 //   - six products of such values and canonical key residues sum below
 //     132 P^2 < 4P * 2^32, the input range of one Montgomery reduction to
 //     [0, 4P) (one reduction per accumulated coefficient);
-//   - the inverse transform's values stay in [0, 2P) with one conditional
-//     subtract per butterfly (unsigned min).
+//   - the inverse transform reduces only every third or fourth stage: a
+//     Gentleman-Sande sum doubles the bound, and inputs below 4P may double
+//     three times (32P < 2^32) before a Shoup product by 1 brings them back
+//     below 2P.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -57,6 +59,12 @@ static_assert(P1 < 2 * P2, "CRT difference range");
 __device__ __forceinline__ uint32_t shoup(uint32_t y, uint32_t w, uint32_t wp, uint32_t p) {
   const uint32_t q = __umulhi(y, wp);
   return w * y - q * p;
+}
+
+// x mod p in [0, 2p) for any 32-bit x: the Shoup product by 1 (whose
+// quotient is floor(2^32 / p)).
+__device__ __forceinline__ uint32_t reduce_2p(uint32_t x, uint32_t p) {
+  return shoup(x, 1u, (uint32_t)((1ull << 32) / p), p);
 }
 
 // x - m if x >= m, else x (for x < 2m): one subtract and one unsigned min.

@@ -13,8 +13,9 @@
 //
 // Butterflies are lazy (Harvey): the forward transform never reduces (each
 // stage raises the bound by 2P: inputs below 2P end below 22P, which the
-// primes keep below 2^32), the inverse keeps its values in [0, 2P); twiddles
-// carry their Shoup quotient floor(w 2^32 / P).
+// primes keep below 2^32); the inverse takes inputs below 4P, lets its sums
+// double the bound and reduces them at three of its ten stages (inv_reduces),
+// ending below 2P.  Twiddles carry their Shoup quotient floor(w 2^32 / P).
 //
 // Three register layouts keep every butterfly inside a lane; two LDS
 // transposes per transform move between them:
@@ -74,12 +75,35 @@ __device__ __forceinline__ void bfly_ct(uint32_t& x, uint32_t& y, uint32_t w, ui
   x = u + t;
   y = u - t + 2 * p;
 }
-// Gentleman-Sande with a negated twiddle -w: (x, y) -> (x + y, (y - x) w); in and out in [0, 2P).
+// Gentleman-Sande with a negated twiddle -w: (x, y) -> (x + y, (y - x) w) for
+// inputs below B P.  The product is in [0, 2P); the sum is below 2B P, or with
+// RED reduced to [0, 2P).
+template <int B, bool RED>
 __device__ __forceinline__ void bfly_gs_neg(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp, uint32_t p) {
   const uint32_t u = x, v = y;
-  x = csub(u + v, 2 * p);
-  y = shoup(v - u + 2 * p, w, wp, p);
+  x = RED ? reduce_2p(u + v, p) : u + v;
+  y = shoup(v - u + (uint32_t)B * p, w, wp, p);
 }
+
+// Bounds of the inverse stages (run from S = 9 down to 0), in multiples of P:
+// the input bound of stage S and whether it reduces its sums.  Inputs start
+// below 4P; a stage's outputs are below twice its input bound, or 2P if it
+// reduces; no sum reaches 32P.
+__host__ __device__ constexpr int inv_bound(int S) {
+  return S == 9 ? 4 : S == 8 ? 8 : S == 7 ? 16 : S == 6 ? 2 : S == 5 ? 4 : S == 4 ? 8 : S == 3 ? 16 : S == 2 ? 2 : S == 1 ? 4 : 8;
+}
+__host__ __device__ constexpr bool inv_reduces(int S) { return S == 7 || S == 3 || S == 0; }
+__host__ __device__ constexpr bool inv_bounds_hold() {
+  for (int S = 9; S >= 0; --S) {
+    if (2 * inv_bound(S) > 32) return false;
+    const int out = inv_reduces(S) ? 2 : 2 * inv_bound(S);
+    if (S > 0 && inv_bound(S - 1) != out) return false;
+    if (S == 0 && out != 2) return false;
+  }
+  return inv_bound(9) == 4;
+}
+static_assert(inv_bounds_hold(), "inverse-transform ranges");
+static_assert(32ull * P1 < (1ull << 32) && 32ull * P2 < (1ull << 32), "inverse sums overflow");
 
 // The eight butterflies of a stage: register r (bit RB clear) pairs with
 // r | 2^RB.  All twiddle reads of the stage are issued before the first
@@ -111,8 +135,8 @@ __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int r = bfly_reg<RB>(k);
-    bfly_gs_neg(v.a[r], v.a[r | (1 << RB)], w[k].x, w[k].y, P1);
-    bfly_gs_neg(v.b[r], v.b[r | (1 << RB)], w[k].z, w[k].w, P2);
+    bfly_gs_neg<inv_bound(S), inv_reduces(S)>(v.a[r], v.a[r | (1 << RB)], w[k].x, w[k].y, P1);
+    bfly_gs_neg<inv_bound(S), inv_reduces(S)>(v.b[r], v.b[r | (1 << RB)], w[k].z, w[k].w, P2);
   }
 }
 
@@ -135,7 +159,7 @@ __device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, cons
   fwd_stage<9, lay_c, 0>(v, tw, lane);
 }
 
-// Inverse without 1/N: layout C (values < 2P) -> layout A (values < 2P).
+// Inverse without 1/N: layout C (values < 4P) -> layout A (values < 2P).
 __device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, const Tw* __restrict__ gtw, int lane) {
   inv_stage<9, lay_c, 0>(v, tw, lane);
   inv_stage<8, lay_c, 1>(v, tw, lane);
@@ -227,7 +251,7 @@ __device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tws, 
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int r = bfly_reg<RB>(k);
-    bfly_gs_neg(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
+    bfly_gs_neg<inv_bound(S), inv_reduces(S)>(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
   }
 }
 
