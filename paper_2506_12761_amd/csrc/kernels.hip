@@ -41,7 +41,9 @@ __global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t
     uint32_t* dst = bk_ntt + (size_t)poly * 2 * RING_N;  // plane of P1, then plane of P2
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const uint32_t a = v.a[r] % P1, b = v.b[r] % P2;  // lazy forward output (< 22P), once per key
+      // Canonical residues of the lazy signed forward output (|v| < 16P), once per key.
+      const uint32_t a = (uint32_t)((int32_t)v.a[r] + 16 * (int32_t)P1) % P1;
+      const uint32_t b = (uint32_t)((int32_t)v.b[r] + 16 * (int32_t)P2) % P2;
       dst[r * 64 + lane] = csub(shoup(a, scale.x, scale.y, P1), P1);
       dst[RING_N + r * 64 + lane] = csub(shoup(b, scale.z, scale.w, P2), P2);
     }
@@ -63,6 +65,14 @@ __global__ void ksk_relayout_kernel(const uint32_t* __restrict__ in, uint32_t* _
 // Blind rotation + sample extraction, one wavefront per item.
 // ---------------------------------------------------------------------------
 constexpr uint32_t DEC_OFFSET = (1u << 31) + (1u << 24) + (1u << 17) + (1u << 10);
+// Balanced digit l of D (with DEC_OFFSET added) is its 7-bit field minus 64,
+// i.e. the field with bit 6 flipped read as a signed 7-bit number: flipping
+// those bits once per coefficient lets one signed bit-field extract give
+// each digit.
+constexpr uint32_t DIGIT_FLIP = (1u << 31) | (1u << 24) | (1u << 17);
+__device__ __forceinline__ uint32_t digit_of(uint32_t d_flipped, int shift) {
+  return (uint32_t)__builtin_amdgcn_sbfe((int)d_flipped, (unsigned)shift, (unsigned)BG_BIT);
+}
 
 // Global-address-space views: loads through them are global (not flat)
 // loads, so they are not counted by the LDS wait of the transposes.
@@ -76,7 +86,7 @@ template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict__ items, uint32_t count,
                                                          const Tw* __restrict__ tw_fwd) {
   constexpr bool kPrefetchKey = WAVES <= 4, kWideAcc = WAVES <= 4;
-  using Acc = typename std::conditional<kWideAcc, uint64_t, uint32_t>::type;
+  using Acc = typename std::conditional<kWideAcc, int64_t, uint32_t>::type;
   __shared__ Tw s_tw[RING_N];                   // twiddles of both primes (16 KB)
   __shared__ uint2 s_buf[WAVES][RING_N];        // per-wave transpose scratch
   __shared__ uint32_t s_acc[WAVES][2][RING_N];  // per-wave accumulator (A, B), coefficient order
@@ -119,11 +129,11 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
       if (ab == 0) continue;
       // External product BK_i x (X^ab acc - acc): the six digit polynomials are
       // transformed one at a time and multiplied into the accumulators.
-      //  - wide (64-bit) accumulators take the lazy transform values (< 22P):
-      //    six products stay below 4P * 2^32, the input range of one Montgomery
-      //    reduction to [0, 4P) at the end;
-      //  - narrow (32-bit) accumulators reduce each product (< 22P^2 < P * 2^32)
-      //    to [0, P) and sum lazily (six terms < 6P < 2^32).
+      //  - wide (64-bit) accumulators take the lazy signed transform values
+      //    (|x| < 16P): one Montgomery reduction of the six products at the
+      //    end gives (-4P, 4P);
+      //  - narrow (32-bit) accumulators reduce each product (|x b| < 16P^2)
+      //    into (-5P/4, P/4 + 1) and sum the six lazily.
       Acc m0a[16], m0b[16], m1a[16], m1b[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) m0a[r] = m0b[r] = m1a[r] = m1b[r] = 0;
@@ -144,7 +154,7 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
-          D[r] = (s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET;
+          D[r] = ((s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET) ^ DIGIT_FLIP;
         }
 #pragma unroll 1
         for (int lev = 0; lev < ELL; ++lev) {
@@ -166,11 +176,7 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
           const int shift = 32 - BG_BIT * (lev + 1);
           Poly2 v;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int32_t d = (int32_t)((D[r] >> shift) & 127u) - 64;
-            v.a[r] = res_of(d, P1);
-            v.b[r] = res_of(d, P2);
-          }
+          for (int r = 0; r < 16; ++r) v.a[r] = v.b[r] = digit_of(D[r], shift);  // signed, |d| <= 64
           ntt_fwd(v, buf, s_tw, tw_fwd, lane);
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
@@ -180,18 +186,17 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
               b1a[r] = k0[2 * RING_N + r * 64 + lane];
               b1b[r] = k0[3 * RING_N + r * 64 + lane];
             }
+            const int64_t da = (int32_t)v.a[r], db = (int32_t)v.b[r];  // |x| < 16P
             if constexpr (kWideAcc) {
-              const uint32_t da = v.a[r], db = v.b[r];  // [0, 22P)
-              m0a[r] += (uint64_t)da * b0a[r];
-              m0b[r] += (uint64_t)db * b0b[r];
-              m1a[r] += (uint64_t)da * b1a[r];
-              m1b[r] += (uint64_t)db * b1b[r];
+              m0a[r] += da * (int32_t)b0a[r];
+              m0b[r] += db * (int32_t)b0b[r];
+              m1a[r] += da * (int32_t)b1a[r];
+              m1b[r] += db * (int32_t)b1b[r];
             } else {
-              const uint32_t da = v.a[r], db = v.b[r];  // [0, 22P)
-              m0a[r] += redc((uint64_t)da * b0a[r], P1, P1_INV);
-              m0b[r] += redc((uint64_t)db * b0b[r], P2, P2_INV);
-              m1a[r] += redc((uint64_t)da * b1a[r], P1, P1_INV);
-              m1b[r] += redc((uint64_t)db * b1b[r], P2, P2_INV);
+              m0a[r] += redc_s(da * (int32_t)b0a[r], P1, P1_INV);
+              m0b[r] += redc_s(db * (int32_t)b0b[r], P2, P2_INV);
+              m1a[r] += redc_s(da * (int32_t)b1a[r], P1, P1_INV);
+              m1b[r] += redc_s(db * (int32_t)b1b[r], P2, P2_INV);
             }
           }
         }
@@ -201,12 +206,12 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
         Poly2 v;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          if constexpr (kWideAcc) {  // [0, 4P), the inverse transform's input range
-            v.a[r] = redc(c ? m1a[r] : m0a[r], P1, P1_INV);
-            v.b[r] = redc(c ? m1b[r] : m0b[r], P2, P2_INV);
-          } else {  // [0, 6P) -> [0, 4P)
-            v.a[r] = csub(c ? m1a[r] : m0a[r], 4 * P1);
-            v.b[r] = csub(c ? m1b[r] : m0b[r], 4 * P2);
+          if constexpr (kWideAcc) {  // (-4P, 4P), the inverse transform's input range
+            v.a[r] = redc_s(c ? m1a[r] : m0a[r], P1, P1_INV);
+            v.b[r] = redc_s(c ? m1b[r] : m0b[r], P2, P2_INV);
+          } else {  // |sum| < 7.5P -> (-P/2, 3P/2)
+            v.a[r] = reduce_s(c ? m1a[r] : m0a[r], P1);
+            v.b[r] = reduce_s(c ? m1b[r] : m0b[r], P2);
           }
         }
         ntt_inv(v, buf, s_tw, tw_fwd, lane);
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
         for (int r = 0; r < 16; ++r) old[r] = poly[r * 64 + lane];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) poly[r * 64 + lane] = old[r] + crt_lift_u32(csub(v.a[r], P1), csub(v.b[r], P2));
+        for (int r = 0; r < 16; ++r) poly[r * 64 + lane] = old[r] + crt_lift_s(v.a[r], v.b[r]);
       }
     }
     wave_lds_sync();
@@ -251,10 +256,10 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
     const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
     if (SKIP && ab == 0) continue;  // the same decision in both wavefronts: abar is shared
-    // 64-bit accumulators of the two output polynomials mod P: six products of
-    // transform values (< 22P) and key residues (< P) stay below 4P * 2^32, so
-    // one reduction at the end gives [0, 4P), the inverse transform's input range.
-    uint64_t m0[16], m1[16];
+    // Signed 64-bit accumulators of the two output polynomials mod P: six
+    // products of transform values (|x| < 16P) and key residues (< P); one
+    // reduction at the end gives (-4P, 4P), the inverse transform's input range.
+    int64_t m0[16], m1[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;
 #pragma unroll 1
@@ -271,7 +276,7 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
-        D[r] = (s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET;
+        D[r] = ((s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET) ^ DIGIT_FLIP;
       }
 #pragma unroll 1
       for (int lev = 0; lev < ELL; ++lev) {
@@ -285,16 +290,14 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
           b1[r] = k0[2 * RING_N + r * 64 + lane];
         }
         const int shift = 32 - BG_BIT * (lev + 1);
-        // Balanced digit d in [-64, 63] as d + P in [P - 64, P + 63]: below 2P,
-        // the input bound the forward transform's ranges start from.
         uint32_t x[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = ((D[r] >> shift) & 127u) + (P - 64);
+        for (int r = 0; r < 16; ++r) x[r] = digit_of(D[r], shift);  // balanced digit, signed
         ntt_fwd1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          m0[r] += (uint64_t)x[r] * b0[r];
-          m1[r] += (uint64_t)x[r] * b1[r];
+          m0[r] += (int64_t)(int32_t)x[r] * (int32_t)b0[r];
+          m1[r] += (int64_t)(int32_t)x[r] * (int32_t)b1[r];
         }
       }
     }
@@ -304,17 +307,17 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     constexpr int KEEP = PR;
     uint32_t keep[16], x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = redc(KEEP ? m1[r] : m0[r], P, PINV);
+    for (int r = 0; r < 16; ++r) x[r] = redc_s(KEEP ? m1[r] : m0[r], P, PINV);
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      keep[r] = csub(x[r], P);
-      x[r] = redc(KEEP ? m0[r] : m1[r], P, PINV);
+      keep[r] = x[r];  // in (-P/2, 3P/2): the lift takes lazy residues
+      x[r] = redc_s(KEEP ? m0[r] : m1[r], P, PINV);
     }
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
     wave_lds_sync();  // the transform's last reads of buf are done
 #pragma unroll
-    for (int r = 0; r < 16; ++r) buf[r * 64 + lane] = csub(x[r], P);
+    for (int r = 0; r < 16; ++r) buf[r * 64 + lane] = x[r];
     __syncthreads();  // both wavefronts have parked their residues
     uint32_t* poly = acc + KEEP * RING_N;
     uint32_t old[16], oth[16];
@@ -326,7 +329,7 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-      poly[r * 64 + lane] = old[r] + (PR == 0 ? crt_lift_u32(keep[r], oth[r]) : crt_lift_u32(oth[r], keep[r]));
+      poly[r * 64 + lane] = old[r] + (PR == 0 ? crt_lift_s(keep[r], oth[r]) : crt_lift_s(oth[r], keep[r]));
     __syncthreads();  // accumulator updated; parked residues consumed
   }
 }
@@ -421,9 +424,9 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
     const uint32_t ab = __builtin_amdgcn_readfirstlane((uint32_t)abar[i]);
     if (ab == 0) continue;  // the same decision in all four wavefronts: abar is shared
-    // Three products of transform values (< 22P) and key residues (< P) per
-    // output: below 66 P^2 < 2P * 2^32, so one reduction gives [0, 2P).
-    uint64_t m0[16], m1[16];
+    // Three products of transform values (|x| < 16P) and key residues (< P)
+    // per output: one reduction gives (-2P, 2P).
+    int64_t m0[16], m1[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;
     {
@@ -439,7 +442,7 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
-        D[r] = (s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET;
+        D[r] = ((s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET) ^ DIGIT_FLIP;
       }
 #pragma unroll 1
       for (int lev = 0; lev < ELL; ++lev) {
@@ -453,12 +456,12 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
         const int shift = 32 - BG_BIT * (lev + 1);
         uint32_t x[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = ((D[r] >> shift) & 127u) + (P - 64);
+        for (int r = 0; r < 16; ++r) x[r] = digit_of(D[r], shift);  // balanced digit, signed
         ntt_fwd1<PR>(x, buf, tws, gtw2, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          m0[r] += (uint64_t)x[r] * b0[r];
-          m1[r] += (uint64_t)x[r] * b1[r];
+          m0[r] += (int64_t)(int32_t)x[r] * (int32_t)b0[r];
+          m1[r] += (int64_t)(int32_t)x[r] * (int32_t)b1[r];
         }
       }
     }
@@ -466,8 +469,8 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
     uint32_t x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      xbuf[r * 64 + lane] = redc(H ? m0[r] : m1[r], P, PINV);  // [0, 2P)
-      x[r] = redc(H ? m1[r] : m0[r], P, PINV);
+      xbuf[r * 64 + lane] = redc_s(H ? m0[r] : m1[r], P, PINV);  // (-2P, 2P)
+      x[r] = redc_s(H ? m1[r] : m0[r], P, PINV);
     }
     __syncthreads();  // B1
     uint32_t oth[16];
@@ -475,14 +478,14 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
     for (int r = 0; r < 16; ++r) oth[r] = half_partner_xbuf[r * 64 + lane];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] += oth[r];  // [0, 4P)
+    for (int r = 0; r < 16; ++r) x[r] += oth[r];  // (-4P, 4P)
     ntt_inv1<PR>(x, buf, tws, gtw2, lane);
     // Wave (0, H) lifts registers 0..7, wave (1, H) registers 8..15: each parks
     // the half the other one lifts.
     wave_lds_sync();  // the transform's last reads of buf are done
     constexpr int MINE = PR * 8, THEIRS = 8 - PR * 8;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) buf[(THEIRS + r) * 64 + lane] = csub(x[THEIRS + r], P);
+    for (int r = 0; r < 8; ++r) buf[(THEIRS + r) * 64 + lane] = x[THEIRS + r];  // lazy: the lift takes (-P/2, 3P/2)
     __syncthreads();  // B2
     uint32_t* poly = acc + H * RING_N;
     uint32_t old[8], o2[8];
@@ -494,8 +497,8 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const uint32_t mine = csub(x[MINE + r], P);
-      poly[(MINE + r) * 64 + lane] = old[r] + (PR == 0 ? crt_lift_u32(mine, o2[r]) : crt_lift_u32(o2[r], mine));
+      const uint32_t mine = x[MINE + r];
+      poly[(MINE + r) * 64 + lane] = old[r] + (PR == 0 ? crt_lift_s(mine, o2[r]) : crt_lift_s(o2[r], mine));
     }
     __syncthreads();  // B3
   }

@@ -33,9 +33,12 @@ __global__ __launch_bounds__(PEAK_THREADS) void butterfly_peak_kernel(uint32_t* 
 #pragma unroll
   for (int r = 0; r < 16; ++r) x[r] = ((seed ^ (tid * 16u + r)) * 2654435761u) % p;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    w[k] = ((seed + tid) * (2u * k + 3u) + 12345u * k) % p;
-    wp[k] = (uint32_t)(((uint64_t)w[k] << 32) / p);
+  for (int k = 0; k < 8; ++k) {  // signed twiddles |w| < p/2 with floor(w 2^32 / p), as the tables hold
+    const int64_t w0 = ((seed + tid) * (2u * k + 3u) + 12345u * k) % p;
+    const int64_t ws = w0 > p / 2 ? w0 - (int64_t)p : w0;
+    const int64_t n = ws * ((int64_t)1 << 32);
+    w[k] = (uint32_t)(int32_t)ws;
+    wp[k] = (uint32_t)(int32_t)(n / (int64_t)p - ((n % (int64_t)p != 0 && n < 0) ? 1 : 0));
     // Opaque from here on, as twiddles read from memory are: otherwise the
     // compiler folds their derivation into the products.
     asm volatile("" : "+v"(w[k]), "+v"(wp[k]));

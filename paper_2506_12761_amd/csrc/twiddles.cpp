@@ -34,15 +34,20 @@ uint64_t generator(uint64_t p) {
 
 }  // namespace
 
+// Entry m: psi^brv10(m) mod each prime as its signed representative
+// w in (-p/2, p/2), and floor(w 2^32 / p) (rounded down for negative w too).
 void make_twiddles(uint32_t* tw) {
   const uint32_t primes[2] = {P1, P2};
   for (int k = 0; k < 2; ++k) {
-    const uint64_t p = primes[k];
+    const int64_t p = primes[k];
     const uint64_t psi = pow_mod(generator(p), (p - 1) / 2048, p);  // order 2048
     for (uint32_t m = 0; m < (uint32_t)RING_N; ++m) {
-      const uint64_t w = pow_mod(psi, brv10(m), p);
-      tw[4 * m + 2 * k] = (uint32_t)w;
-      tw[4 * m + 2 * k + 1] = (uint32_t)((w << 32) / p);
+      const int64_t w0 = (int64_t)pow_mod(psi, brv10(m), p);
+      const int64_t w = w0 > p / 2 ? w0 - p : w0;
+      const int64_t n = w * ((int64_t)1 << 32);
+      const int64_t q = n / p - ((n % p != 0 && n < 0) ? 1 : 0);
+      tw[4 * m + 2 * k] = (uint32_t)(int32_t)w;
+      tw[4 * m + 2 * k + 1] = (uint32_t)(int32_t)q;
     }
   }
 }

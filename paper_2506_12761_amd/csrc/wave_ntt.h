@@ -11,11 +11,12 @@
 // It reads the forward table too: psi^-brv10(2^s + i) = -psi^brv10(2^(s+1) - 1 - i),
 // so its stage s uses entry 2^(s+1) - 1 - i with the subtraction reversed.
 //
-// Butterflies are lazy (Harvey): the forward transform never reduces (each
-// stage raises the bound by 2P: inputs below 2P end below 22P, which the
-// primes keep below 2^32); the inverse takes inputs below 4P, lets its sums
-// double the bound and reduces them at three of its ten stages (inv_reduces),
-// ending below 2P.  Twiddles carry their Shoup quotient floor(w 2^32 / P).
+// Butterflies are lazy and work on signed residues (rns.h): the forward
+// transform never reduces (each stage raises the magnitude bound by 3P/2:
+// digits end below 16P); the inverse takes inputs below 4P in magnitude, lets
+// its sums double the bound and reduces them at three of its ten stages
+// (inv_reduces), ending in (-P/2, 3P/2).  Twiddles are signed (|w| < P/2) and
+// carry their Shoup quotient floor(w 2^32 / P).
 //
 // Three register layouts keep every butterfly inside a lane; two LDS
 // transposes per transform move between them:
@@ -29,7 +30,8 @@
 
 namespace vlp {
 
-// Twiddle table entry: {w mod P1, Shoup(w1), w mod P2, Shoup(w2)}.
+// Twiddle table entry: {w1, Shoup(w1), w2, Shoup(w2)}, w_i the signed
+// representative (|w_i| < P_i / 2) of the twiddle mod P_i.
 using Tw = uint4;
 
 __device__ __forceinline__ int lay_a(int lane, int r) { return r * 64 + lane; }
@@ -67,28 +69,29 @@ __device__ __forceinline__ void wave_transpose(Poly2& v, uint2* buf, int lane) {
   }
 }
 
-// Cooley-Tukey: (x, y) -> (x + w y, x - w y) with w y taken in [0, 2P): for
-// x below B (any y) both outputs are below B + 2P.  No reduction.
-__device__ __forceinline__ void bfly_ct(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp, uint32_t p) {
+// Cooley-Tukey: (x, y) -> (x + w y, x - w y) with w y taken in (-P/2, 3P/2):
+// for |x| below B (any |y| < 2^31) both outputs are below B + 3P/2 in
+// magnitude.  No reduction.
+__device__ __forceinline__ void bfly_ct(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wq, uint32_t p) {
   const uint32_t u = x;
-  const uint32_t t = shoup(y, w, wp, p);
+  const uint32_t t = shoup_s(y, w, wq, p);
   x = u + t;
-  y = u - t + 2 * p;
+  y = u - t;
 }
 // Gentleman-Sande with a negated twiddle -w: (x, y) -> (x + y, (y - x) w) for
-// inputs below B P.  The product is in [0, 2P); the sum is below 2B P, or with
-// RED reduced to [0, 2P).
+// inputs below B P in magnitude.  The product is in (-P/2, 3P/2); the sum is
+// below 2B P, or with RED reduced into (-P/2, 3P/2).
 template <int B, bool RED>
-__device__ __forceinline__ void bfly_gs_neg(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp, uint32_t p) {
+__device__ __forceinline__ void bfly_gs_neg(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wq, uint32_t p) {
   const uint32_t u = x, v = y;
-  x = RED ? reduce_2p(u + v, p) : u + v;
-  y = shoup(v - u + (uint32_t)B * p, w, wp, p);
+  x = RED ? reduce_s(u + v, p) : u + v;
+  y = shoup_s(v - u, w, wq, p);
 }
 
 // Bounds of the inverse stages (run from S = 9 down to 0), in multiples of P:
-// the input bound of stage S and whether it reduces its sums.  Inputs start
-// below 4P; a stage's outputs are below twice its input bound, or 2P if it
-// reduces; no sum reaches 32P.
+// the magnitude bound of stage S's inputs and whether it reduces its sums.
+// Inputs start below 4P; a stage's outputs are below twice its input bound,
+// or 2P if it reduces; no sum or difference reaches 32P.
 __host__ __device__ constexpr int inv_bound(int S) {
   return S == 9 ? 4 : S == 8 ? 8 : S == 7 ? 16 : S == 6 ? 2 : S == 5 ? 4 : S == 4 ? 8 : S == 3 ? 16 : S == 2 ? 2 : S == 1 ? 4 : 8;
 }
@@ -103,7 +106,14 @@ __host__ __device__ constexpr bool inv_bounds_hold() {
   return inv_bound(9) == 4;
 }
 static_assert(inv_bounds_hold(), "inverse-transform ranges");
-static_assert(32ull * P1 < (1ull << 32) && 32ull * P2 < (1ull << 32), "inverse sums overflow");
+static_assert(32ull * P1 < (1ull << 31) && 32ull * P2 < (1ull << 31), "inverse sums overflow");
+
+// Stages 0..3 read wavefront-uniform twiddles into scalar registers.  A
+// signed high product with a scalar operand is expanded by the compiler into
+// an unsigned one plus two sign corrections (four extra instructions per
+// butterfly); a copy of the quotient into a vector register (one move per
+// distinct twiddle) keeps it to one v_mul_hi_i32.
+__device__ __forceinline__ void vgpr_quotient(uint32_t& wq) { asm("" : "+v"(wq)); }
 
 // The eight butterflies of a stage: register r (bit RB clear) pairs with
 // r | 2^RB.  All twiddle reads of the stage are issued before the first
@@ -117,7 +127,10 @@ template <int S, int (*LAY)(int, int), int RB>
 __device__ __forceinline__ void fwd_stage(Poly2& v, const Tw* tw, int lane) {
   Tw w[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = tw[(1 << S) + (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+  for (int k = 0; k < 8; ++k) {
+    w[k] = tw[(1 << S) + (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+    if (S < 4) vgpr_quotient(w[k].y), vgpr_quotient(w[k].w);
+  }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -130,7 +143,10 @@ template <int S, int (*LAY)(int, int), int RB>
 __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
   Tw w[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = tw[(2 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+  for (int k = 0; k < 8; ++k) {
+    w[k] = tw[(2 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+    if (S < 4) vgpr_quotient(w[k].y), vgpr_quotient(w[k].w);
+  }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -140,7 +156,7 @@ __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
   }
 }
 
-// Forward: layout A (coefficient order, values < 2P) -> layout C (transform order, < 22P).
+// Forward: layout A (coefficient order, |values| <= 64) -> layout C (transform order, |values| < 16P).
 // Stages 0..3 use wavefront-uniform twiddles (their index depends only on the
 // register), read through `gtw` (the table in global memory: scalar loads into
 // SGPRs); the other stages read the LDS copy `tw` per lane.
@@ -159,7 +175,7 @@ __device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, cons
   fwd_stage<9, lay_c, 0>(v, tw, lane);
 }
 
-// Inverse without 1/N: layout C (values < 4P) -> layout A (values < 2P).
+// Inverse without 1/N: layout C (|values| < 4P) -> layout A (values in (-P/2, 3P/2)).
 __device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, const Tw* __restrict__ gtw, int lane) {
   inv_stage<9, lay_c, 0>(v, tw, lane);
   inv_stage<8, lay_c, 1>(v, tw, lane);
@@ -231,6 +247,7 @@ __device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tws, 
   for (int k = 0; k < 8; ++k) {
     const int o = LAY(lane, bfly_reg<RB>(k)) >> (10 - S);
     w[k] = S < 4 ? gtw2[2 * ((1 << S) + o) + PR] : tws[(1 << S) + tw_perm(S, o)];
+    if (S < 4) vgpr_quotient(w[k].y);
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -246,6 +263,7 @@ __device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tws, 
   for (int k = 0; k < 8; ++k) {
     const int o = (1 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S));  // entry 2^(S+1) - 1 - i
     w[k] = S < 4 ? gtw2[2 * ((1 << S) + o) + PR] : tws[(1 << S) + tw_perm(S, o)];
+    if (S < 4) vgpr_quotient(w[k].y);
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
