@@ -41,11 +41,12 @@ __device__ __forceinline__ int lay_c(int lane, int r) {
 }
 __device__ __forceinline__ int lds_slot(int j) { return j ^ ((j >> 6) & 15); }
 
-// Orders LDS accesses of one wavefront: every lane's earlier LDS writes are
-// complete before any later LDS access of the wave is issued.
+// Orders LDS accesses of one wavefront across its lanes.  The LDS performs
+// one wavefront's operations in issue order, so a later read sees every
+// lane's earlier write without waiting for it: the fences and the barrier
+// only keep the compiler from moving accesses across this point.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
