@@ -33,13 +33,18 @@ sys.path.insert(0, ROOT)
 # 6 forward + 2 inverse 1024-point transforms of 5,120 butterflies and
 # 12 x 1,024 pointwise products): 630 * (8 * 5120 + 12 * 1024).
 MODMUL_PER_BR = 630 * (8 * 5120 + 12 * 1024)  # 33,546,240
-# Integer VALU peak of MI355X: 256 CUs x 64 lanes/clock x 2.4 GHz, divided by
-# the VALU operations of one exact multiplication modulo a 64-bit prime on
-# gfx950 (Goldilocks: 4 32x32->64 multiply-adds + 12 adds/selects for the
-# 2^64 = 2^32 - 1 fold), the reference modular-multiplication cost.
+# Integer VALU peak of MI355X for that unit of work: 256 CUs x 64 lanes x
+# 2.4 GHz = 39.3 T VALU lane-instructions/s, divided by the instructions of
+# one exact modular multiplication.  The products need a modulus above
+# 2^51.6; the cheapest exact form on the 32-bit VALU is one residue
+# butterfly per prime of a two-prime RNS (26-bit primes), each a signed
+# Shoup product (v_mul_hi_i32, v_mul_lo_u32, v_mad_u64_u32) plus one add and
+# one subtract: 2 x 5 = 10 instructions.  (A 64-bit Goldilocks multiply
+# takes about 16.)
 VALU_LANE_OPS = 256 * 64 * 2.4e9
-OPS_PER_MODMUL = 16
-PEAK_MODMUL = VALU_LANE_OPS / OPS_PER_MODMUL  # 2.4576e12 modmul/s
+OPS_PER_RESIDUE_BUTTERFLY = 5
+RESIDUES_PER_MODMUL = 2
+PEAK_MODMUL = VALU_LANE_OPS / (OPS_PER_RESIDUE_BUTTERFLY * RESIDUES_PER_MODMUL)  # 3.932e12 modmul/s
 
 # A workload is one or more programs run together (their levels merged).
 # HBM-side traffic of the blind-rotation kernel per launch on the default
@@ -477,12 +482,13 @@ def main():
                                4: "br4_kernel"}[launch["br_waves_per_rotation"]],
                     "launches": br["launches"], "avg_launch_ms": avg_ms,
                     "ks_kernel_ms_share": prof["ks"]["ms"] / max(1e-9, prof["ks"]["ms"] + br["ms"])}
-        # Beside the derived peak: the measured rate of the transforms' own butterflies
-        # (register-resident, every CU busy, the 6:2 forward:inverse mix of a CMux).
+        # Beside the derived peak: the measured rate of the transforms' own residue
+        # butterflies (register-resident, every CU busy, the 6:2 forward:inverse mix of
+        # a CMux), two of which make one modular multiplication.
         mp = vlp.vlp_measure_modmul_peak(0)
-        roofline["peak_measured"] = mp["mixed"] / 1e12
-        roofline["frac_of_peak_measured"] = achieved / mp["mixed"]
-        log("measured butterfly peak: %.3f T/s forward, %.3f T/s inverse, %.3f T/s mixed"
+        roofline["peak_measured"] = mp["mixed"] / RESIDUES_PER_MODMUL / 1e12
+        roofline["frac_of_peak_measured"] = achieved / (mp["mixed"] / RESIDUES_PER_MODMUL)
+        log("measured residue-butterfly peak: %.3f T/s forward, %.3f T/s inverse, %.3f T/s mixed"
             % (mp["fwd"] / 1e12, mp["inv"] / 1e12, mp["mixed"] / 1e12))
 
     cpu = None

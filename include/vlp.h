@@ -257,12 +257,14 @@ vlp_status vlp_profile_read(vlp_ctx *ctx, vlp_kernel_stats *br, vlp_kernel_stats
 
 /* ---- Measured arithmetic peak.  The count a blind rotation is priced by is
  * its modular multiplications (per CMux of Section 2.2: 8 negacyclic
- * transforms of 512 x 10 butterflies and 12 x 1024 key products).  This call
- * measures the rate at which HIP device `device` runs the transforms' own
- * butterflies (lazy forward Cooley-Tukey and inverse Gentleman-Sande with
- * Shoup products, one multiplication each) on register-resident values with
- * every CU busy: *fwd_per_s and *inv_per_s for each kind, *mixed_per_s for
- * the 6:2 forward:inverse mix of a CMux (multiplications per second).  It
+ * transforms of 512 x 10 butterflies and 12 x 1024 key products), each
+ * computed as one residue butterfly per prime of the two-prime residue
+ * system.  This call measures the rate at which HIP device `device` runs the
+ * transforms' own residue butterflies (lazy signed forward Cooley-Tukey and
+ * inverse Gentleman-Sande with Shoup products) on register-resident values
+ * with every CU busy: *fwd_per_s and *inv_per_s for each kind, *mixed_per_s
+ * for the 6:2 forward:inverse mix of a CMux (residue butterflies per second;
+ * halve for modular multiplications per second).  It
  * blocks for about 0.1 s, allocates and frees a small device buffer and a
  * stream of its own, and needs no context.  VLP_EINVAL for a null output or
  * a bad device; VLP_EHIP if a HIP call fails (no message: there is no

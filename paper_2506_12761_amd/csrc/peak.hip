@@ -3,13 +3,14 @@
 // The algorithmic count of a blind rotation is its modular multiplications:
 // per CMux, 8 transforms of (N/2) log2 N butterflies (one multiplication
 // each) and 12 N pointwise key products (Section 2.2: the external product
-// of a CMux, computed with negacyclic transforms).  The bound such a count
-// is priced against can be derived from the instruction set (lanes x clock
-// divided by the VALU instructions of one multiplication) or measured: this
-// file measures it, with the very butterflies the transforms execute
-// (wave_ntt.h: lazy Cooley-Tukey forward, Gentleman-Sande inverse, Shoup
-// products), on register-resident values, every CU busy and no memory
-// traffic inside the loop.
+// of a CMux, computed with negacyclic transforms); each is carried out as one
+// residue butterfly per prime of the two-prime residue system.  The bound
+// such a count is priced against can be derived from the instruction set
+// (lanes x clock divided by the VALU instructions of one multiplication) or
+// measured: this file measures it, with the very residue butterflies the
+// transforms execute (wave_ntt.h: lazy signed Cooley-Tukey forward,
+// Gentleman-Sande inverse, Shoup products), on register-resident values,
+// every CU busy and no memory traffic inside the loop.
 #include <hip/hip_runtime.h>
 
 #include "vlp.h"
