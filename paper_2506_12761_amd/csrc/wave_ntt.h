@@ -225,6 +225,39 @@ __device__ __forceinline__ void wave_transpose1(uint32_t (&x)[16], uint32_t* buf
   for (int r = 0; r < 16; ++r) x[r] = buf[lds_slot1(TO(lane, r))];
 }
 
+// Layouts B and C differ only inside each quad of lanes: for lane q = lane & 3
+// and register r = 4g + d, B holds element 16g + 4d + q of the quad's 64 and C
+// holds 16g + 4q + d.  The move between them is a 4 x 4 transpose of (q, d)
+// per register group g, done in registers: two exchange steps (bit 0 of q
+// with bit 0 of d, then bit 1 with bit 1), each output one select whose other
+// operand comes from the partner lane by a quad permutation.  The transpose is
+// its own inverse, so it serves B -> C and C -> B alike.
+template <int XOR>
+__device__ __forceinline__ uint32_t quad_xor(uint32_t v) {
+  constexpr int ctrl = XOR == 1 ? (1 | (0 << 2) | (3 << 4) | (2 << 6))   // quad_perm [1, 0, 3, 2]
+                                : (2 | (3 << 2) | (0 << 4) | (1 << 6));  // quad_perm [2, 3, 0, 1]
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, true);
+}
+// Every lane computes every permuted value before any select: a permutation
+// evaluated under a partial execution mask would read inactive partners.
+__device__ __forceinline__ void quad_transpose(uint32_t (&x)[16], int lane) {
+  const bool q0 = lane & 1, q1 = lane & 2;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    uint32_t* v = x + 4 * g;
+    const uint32_t p0 = quad_xor<1>(v[0]), p1 = quad_xor<1>(v[1]);
+    const uint32_t p2 = quad_xor<1>(v[2]), p3 = quad_xor<1>(v[3]);
+    const uint32_t n0 = q0 ? p1 : v[0], n1 = q0 ? v[1] : p0;
+    const uint32_t n2 = q0 ? p3 : v[2], n3 = q0 ? v[3] : p2;
+    const uint32_t r0 = quad_xor<2>(n0), r1 = quad_xor<2>(n1);
+    const uint32_t r2 = quad_xor<2>(n2), r3 = quad_xor<2>(n3);
+    v[0] = q1 ? r2 : n0;
+    v[1] = q1 ? r3 : n1;
+    v[2] = q1 ? n2 : r0;
+    v[3] = q1 ? n3 : r1;
+  }
+}
+
 // Position of twiddle-table entry 2^S + o inside stage S's slice of a
 // per-prime LDS plane.  Stage S >= 4 reads entry offsets o whose bits hold the
 // lane group h = lane >> 2 (and, in layout C, q = lane & 3) above bits set by
@@ -287,7 +320,7 @@ __device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const
   fwd_stage1<PR, 5, lay_b, 2>(x, tws, gtw2, lane);
   fwd_stage1<PR, 6, lay_b, 1>(x, tws, gtw2, lane);
   fwd_stage1<PR, 7, lay_b, 0>(x, tws, gtw2, lane);
-  wave_transpose1<lay_b, lay_c>(x, buf, lane);
+  quad_transpose(x, lane);  // layout B -> C
   fwd_stage1<PR, 8, lay_c, 1>(x, tws, gtw2, lane);
   fwd_stage1<PR, 9, lay_c, 0>(x, tws, gtw2, lane);
 }
@@ -297,7 +330,7 @@ __device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const
                                          const uint2* __restrict__ gtw2, int lane) {
   inv_stage1<PR, 9, lay_c, 0>(x, tws, gtw2, lane);
   inv_stage1<PR, 8, lay_c, 1>(x, tws, gtw2, lane);
-  wave_transpose1<lay_c, lay_b>(x, buf, lane);
+  quad_transpose(x, lane);  // layout C -> B
   inv_stage1<PR, 7, lay_b, 0>(x, tws, gtw2, lane);
   inv_stage1<PR, 6, lay_b, 1>(x, tws, gtw2, lane);
   inv_stage1<PR, 5, lay_b, 2>(x, tws, gtw2, lane);
