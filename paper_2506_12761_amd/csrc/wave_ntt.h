@@ -18,8 +18,9 @@
 // (inv_reduces), ending in (-P/2, 3P/2).  Twiddles are signed (|w| < P/2) and
 // carry their Shoup quotient floor(w 2^32 / P).
 //
-// Three register layouts keep every butterfly inside a lane; two LDS
-// transposes per transform move between them:
+// Three register layouts keep every butterfly inside a lane; per transform an
+// LDS transpose moves between A and B and an in-register quad transpose
+// (quad_transpose) between B and C (the two-prime form uses LDS for both):
 //   A (coefficient order): j = 64 r + lane                                    stages 0..3
 //   B                      : j = 64 (lane>>2) + 4 r + (lane&3)                 stages 4..7
 //   C (transform order)    : j = 64 (lane>>2) + 16 (r>>2) + 4 (lane&3) + (r&3) stages 8, 9
