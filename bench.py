@@ -321,6 +321,8 @@ def main():
     ap.add_argument("--br-rotations-per-block", type=int, default=0,
                     help="blind rotations per workgroup (1, 2, 4; 8 with one wavefront per rotation)")
     ap.add_argument("--br-blocks", type=int, default=0, help="blind-rotation workgroups per CU the grid is sized for")
+    ap.add_argument("--ks-gates-per-block", type=int, default=0, choices=(0, 4, 8, 16),
+                    help="gates sharing one pass over the key-switching key (0: library default)")
     ap.add_argument("--br-waves-per-rotation", type=int, default=-1, choices=(-1, 0, 1, 2, 4),
                     help="wavefronts per blind rotation (0: automatic by launch size)")
     ap.add_argument("--serve", action="store_true", help="run the serving experiment instead")
@@ -375,11 +377,11 @@ def main():
     if args.tuned:
         from paper_2506_12761_amd import autotune
         log("cached tuning applied: %s" % autotune.load_cached(ctx, args.workload))
-    if args.br_rotations_per_block or args.br_blocks or args.br_waves_per_rotation >= 0:
+    if args.br_rotations_per_block or args.br_blocks or args.br_waves_per_rotation >= 0 or args.ks_gates_per_block:
         t = vlp.vlp_get_tuning(ctx.ctx)
         vlp.vlp_set_tuning(ctx.ctx, args.br_rotations_per_block or t.br_rotations_per_block,
                            args.br_blocks or t.br_blocks_per_cu,
-                           t.ks_gates_per_block,
+                           args.ks_gates_per_block or t.ks_gates_per_block,
                            args.br_waves_per_rotation if args.br_waves_per_rotation >= 0 else t.br_waves_per_rotation)
     t = vlp.vlp_get_tuning(ctx.ctx)
     launch = {"br_waves_per_rotation": t.br_waves_per_rotation, "br_rotations_per_block": t.br_rotations_per_block,
