@@ -233,7 +233,8 @@ vlp_status vlp_program_destroy(vlp_program *prog);
  * br_blocks_per_cu      : workgroups per compute unit a launch is sized for
  *                          (1..64); one launch covers br_blocks_per_cu x
  *                          br_rotations_per_block rotations per CU
- * ks_gates_per_block    : gates sharing one pass over the key-switching key (4, 8, 16) */
+ * ks_gates_per_block    : gates sharing one pass over the key-switching key (4, 8
+ *                          (default), 16) */
 typedef struct {
     uint32_t br_rotations_per_block;
     uint32_t br_blocks_per_cu;

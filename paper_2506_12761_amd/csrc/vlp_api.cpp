@@ -24,7 +24,7 @@ struct vlp_ctx {
   std::string err;
   uint4* tw_fwd = nullptr;  // device twiddle table
   int num_cus = 256;
-  vlp_tuning tune{4, 1, 4, 0};
+  vlp_tuning tune{4, 1, 8, 0};
   // Grow-only scratch for the elementwise calls.
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
