@@ -10,7 +10,7 @@ import sys
 import pytest
 
 sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "capi"))
-import build as capi  # noqa: E402
+import capi_build as capi  # noqa: E402
 
 
 def test_c_program_builds_against_the_abi(tmp_path):
