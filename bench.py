@@ -123,9 +123,24 @@ def cpu_baseline(seconds: float, threads: int):
         counts = list(ex.map(worker, range(threads)))
     el = time.perf_counter() - t0
     total = sum(counts)
+    # One thread, gates one after another: the mean time of one gate.
+    single, t1 = 0, time.perf_counter()
+    while single < 2 or (single < 20 and time.perf_counter() - t1 < 3.0):
+        O.gate(keys, O.AND, cts[single % len(cts), 0], cts[single % len(cts), 1])
+        single += 1
+    single_ms = (time.perf_counter() - t1) * 1e3 / single
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": total / el, "unit": "bootstraps/s", "cores": threads, "kind": "oracle",
             "sample": "%d AND gates (1 blind rotation + 1 key switch each) on uniform ciphertexts, "
-                      "%d threads, %.1f s wall" % (total, threads, el)}
+                      "%d threads, %.1f s wall" % (total, threads, el),
+            "single_thread_ms_per_gate": single_ms, "single_thread_gates": single,
+            "host": {"cpu_model": model, "cpus_available": avail, "cpu_count": os.cpu_count()}}
 
 
 # Query shapes of the paper's four datasets (Table 3: records M, interval or
