@@ -20,7 +20,7 @@ constexpr uint32_t MU = 0x20000000u; // 1/8
 
 // Transformed bootstrapping key: [630][6 rows][2 components][1024] residue
 // pairs (mod P1, mod P2), each polynomial in the NTT's transform order
-// (layout C, stored as [r][lane] so a wave's loads are contiguous), scaled
+// (layout Z, stored as [r][lane] so a wave's loads are contiguous), scaled
 // by 1/1024 and kept in Montgomery form (times 2^32 mod P).
 constexpr size_t BK_ROW_WORDS = (size_t)2 * ELL * 2 * 2 * RING_N;  // one key row i: [6][2][2 primes][1024] words
 constexpr size_t BK_NTT_WORDS = (size_t)LWE_n * BK_ROW_WORDS;

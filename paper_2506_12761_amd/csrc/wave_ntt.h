@@ -18,14 +18,15 @@
 // (inv_reduces), ending in (-P/2, 3P/2).  Twiddles are signed (|w| < P/2) and
 // carry their Shoup quotient floor(w 2^32 / P).
 //
-// Three register layouts keep every butterfly inside a lane; per transform an
-// LDS transpose moves between A and B and an in-register quad transpose
-// (quad_transpose) between B and C (the two-prime form uses LDS for both):
-//   A (coefficient order): j = 64 r + lane                                    stages 0..3
-//   B                      : j = 64 (lane>>2) + 4 r + (lane&3)                 stages 4..7
-//   C (transform order)    : j = 64 (lane>>2) + 16 (r>>2) + 4 (lane&3) + (r&3) stages 8, 9
-// In LDS, element j sits at slot j ^ ((j >> 6) & 15), which spreads each of
-// the three access patterns evenly over the banks.
+// Three register layouts keep every butterfly inside a lane (a = lane & 15,
+// h = lane >> 4):
+//   A (coefficient order): j = 64 r + lane                                  stages 0..3
+//   Y                      : j = 64 a + 4 r + h                              stages 4..7
+//   Z (transform order)    : j = 64 a + 16 h + 4 (r & 3) + (r >> 2)          stages 8, 9
+// An LDS transpose moves between A and Y (in LDS, element j sits at slot
+// lds_slot(j), which spreads both access patterns over distinct banks); Y and
+// Z differ only in two exchanged bit pairs, which the lane-swap instructions
+// move in registers (swap_yz).
 #pragma once
 #include "rns.h"
 
@@ -36,11 +37,16 @@ namespace vlp {
 using Tw = uint4;
 
 __device__ __forceinline__ int lay_a(int lane, int r) { return r * 64 + lane; }
-__device__ __forceinline__ int lay_b(int lane, int r) { return ((lane >> 2) << 6) | (r << 2) | (lane & 3); }
-__device__ __forceinline__ int lay_c(int lane, int r) {
-  return ((lane >> 2) << 6) | ((r >> 2) << 4) | ((lane & 3) << 2) | (r & 3);
+__device__ __forceinline__ int lay_y(int lane, int r) { return ((lane & 15) << 6) | (r << 2) | (lane >> 4); }
+__device__ __forceinline__ int lay_z(int lane, int r) {
+  return ((lane & 15) << 6) | ((lane >> 4) << 4) | ((r & 3) << 2) | (r >> 2);
 }
-__device__ __forceinline__ int lds_slot(int j) { return j ^ ((j >> 6) & 15); }
+// LDS slot of element j: a bijection on each block of 64 (bits 1..4 take the
+// block index, bit 5 takes bit 1).  Writes in layout A (one block per
+// register, every lane a distinct slot of it) and reads in layout Y (64 a + 4 r
+// + h: a and h vary over the lanes) both touch 64 distinct banks, and 32
+// distinct ones in each half of the wavefront.
+__device__ __forceinline__ int lds_slot(int j) { return j ^ (((j >> 6) & 15) << 1) ^ (((j >> 1) & 1) << 5); }
 
 // Orders LDS accesses of one wavefront across its lanes.  The LDS performs
 // one wavefront's operations in issue order, so a later read sees every
@@ -125,6 +131,33 @@ template <int RB>
 __device__ __forceinline__ constexpr int bfly_reg(int k) {
   return ((k >> RB) << (RB + 1)) | (k & ((1 << RB) - 1));
 }
+// Layouts Y and Z differ in two exchanged bit pairs: lane bit 5 with
+// register bit 3 and lane bit 4 with register bit 2.  The lane-swap
+// instructions exchange such a pair for two registers at once:
+// permlane32_swap moves the upper 32 lanes of its first register and the lower
+// 32 lanes of its second past each other, permlane16_swap the odd rows of 16
+// lanes of its first and the even rows of its second.  The exchange is its
+// own inverse, so it serves Y -> Z and Z -> Y alike.
+__device__ __forceinline__ void swap_yz(uint32_t (&x)[16]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {  // register bit 3 <-> lane bit 5
+    const auto t = __builtin_amdgcn_permlane32_swap(x[r], x[r | 8], false, false);
+    x[r] = t[0];
+    x[r | 8] = t[1];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // register bit 2 <-> lane bit 4
+    const int r = bfly_reg<2>(k);
+    const auto t = __builtin_amdgcn_permlane16_swap(x[r], x[r | 4], false, false);
+    x[r] = t[0];
+    x[r | 4] = t[1];
+  }
+}
+__device__ __forceinline__ void swap_yz(Poly2& v) {
+  swap_yz(v.a);
+  swap_yz(v.b);
+}
+
 template <int S, int (*LAY)(int, int), int RB>
 __device__ __forceinline__ void fwd_stage(Poly2& v, const Tw* tw, int lane) {
   Tw w[8];
@@ -158,7 +191,7 @@ __device__ __forceinline__ void inv_stage(Poly2& v, const Tw* tw, int lane) {
   }
 }
 
-// Forward: layout A (coefficient order, |values| <= 64) -> layout C (transform order, |values| < 16P).
+// Forward: layout A (coefficient order, |values| <= 64) -> layout Z (transform order, |values| < 16P).
 // Stages 0..3 use wavefront-uniform twiddles (their index depends only on the
 // register), read through `gtw` (the table in global memory: scalar loads into
 // SGPRs); the other stages read the LDS copy `tw` per lane.
@@ -167,26 +200,26 @@ __device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, cons
   fwd_stage<1, lay_a, 2>(v, gtw, lane);
   fwd_stage<2, lay_a, 1>(v, gtw, lane);
   fwd_stage<3, lay_a, 0>(v, gtw, lane);
-  wave_transpose<lay_a, lay_b>(v, buf, lane);
-  fwd_stage<4, lay_b, 3>(v, tw, lane);
-  fwd_stage<5, lay_b, 2>(v, tw, lane);
-  fwd_stage<6, lay_b, 1>(v, tw, lane);
-  fwd_stage<7, lay_b, 0>(v, tw, lane);
-  wave_transpose<lay_b, lay_c>(v, buf, lane);
-  fwd_stage<8, lay_c, 1>(v, tw, lane);
-  fwd_stage<9, lay_c, 0>(v, tw, lane);
+  wave_transpose<lay_a, lay_y>(v, buf, lane);
+  fwd_stage<4, lay_y, 3>(v, tw, lane);
+  fwd_stage<5, lay_y, 2>(v, tw, lane);
+  fwd_stage<6, lay_y, 1>(v, tw, lane);
+  fwd_stage<7, lay_y, 0>(v, tw, lane);
+  swap_yz(v);  // layout Y -> Z
+  fwd_stage<8, lay_z, 3>(v, tw, lane);
+  fwd_stage<9, lay_z, 2>(v, tw, lane);
 }
 
-// Inverse without 1/N: layout C (|values| < 4P) -> layout A (values in (-P/2, 3P/2)).
+// Inverse without 1/N: layout Z (|values| < 4P) -> layout A (values in (-P/2, 3P/2)).
 __device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, const Tw* __restrict__ gtw, int lane) {
-  inv_stage<9, lay_c, 0>(v, tw, lane);
-  inv_stage<8, lay_c, 1>(v, tw, lane);
-  wave_transpose<lay_c, lay_b>(v, buf, lane);
-  inv_stage<7, lay_b, 0>(v, tw, lane);
-  inv_stage<6, lay_b, 1>(v, tw, lane);
-  inv_stage<5, lay_b, 2>(v, tw, lane);
-  inv_stage<4, lay_b, 3>(v, tw, lane);
-  wave_transpose<lay_b, lay_a>(v, buf, lane);
+  inv_stage<9, lay_z, 2>(v, tw, lane);
+  inv_stage<8, lay_z, 3>(v, tw, lane);
+  swap_yz(v);  // layout Z -> Y
+  inv_stage<7, lay_y, 0>(v, tw, lane);
+  inv_stage<6, lay_y, 1>(v, tw, lane);
+  inv_stage<5, lay_y, 2>(v, tw, lane);
+  inv_stage<4, lay_y, 3>(v, tw, lane);
+  wave_transpose<lay_y, lay_a>(v, buf, lane);
   inv_stage<3, lay_a, 0>(v, gtw, lane);
   inv_stage<2, lay_a, 1>(v, gtw, lane);
   inv_stage<1, lay_a, 2>(v, gtw, lane);
@@ -209,67 +242,28 @@ struct Prime<1> {
   static constexpr uint32_t P = P2, PINV = P2_INV;
 };
 
-// LDS slot of element j for 4-byte transposes: 32 lanes of every layout hit
-// 32 distinct banks (h = j >> 6 goes to bank bits {0,1,4} and {2,3,4} alike).
-__device__ __forceinline__ int lds_slot1(int j) {
-  const int h = j >> 6;
-  return j ^ ((h & 3) | ((h & 3) << 2) | (((h >> 2) & 1) << 4) | (((h >> 3) & 1) << 5));
-}
-
 template <int (*FROM)(int, int), int (*TO)(int, int)>
 __device__ __forceinline__ void wave_transpose1(uint32_t (&x)[16], uint32_t* buf, int lane) {
   wave_lds_sync();  // earlier readers of buf are done
 #pragma unroll
-  for (int r = 0; r < 16; ++r) buf[lds_slot1(FROM(lane, r))] = x[r];
+  for (int r = 0; r < 16; ++r) buf[lds_slot(FROM(lane, r))] = x[r];
   wave_lds_sync();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = buf[lds_slot1(TO(lane, r))];
-}
-
-// Layouts B and C differ only inside each quad of lanes: for lane q = lane & 3
-// and register r = 4g + d, B holds element 16g + 4d + q of the quad's 64 and C
-// holds 16g + 4q + d.  The move between them is a 4 x 4 transpose of (q, d)
-// per register group g, done in registers: two exchange steps (bit 0 of q
-// with bit 0 of d, then bit 1 with bit 1), each output one select whose other
-// operand comes from the partner lane by a quad permutation.  The transpose is
-// its own inverse, so it serves B -> C and C -> B alike.
-template <int XOR>
-__device__ __forceinline__ uint32_t quad_xor(uint32_t v) {
-  constexpr int ctrl = XOR == 1 ? (1 | (0 << 2) | (3 << 4) | (2 << 6))   // quad_perm [1, 0, 3, 2]
-                                : (2 | (3 << 2) | (0 << 4) | (1 << 6));  // quad_perm [2, 3, 0, 1]
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, true);
-}
-// Every lane computes every permuted value before any select: a permutation
-// evaluated under a partial execution mask would read inactive partners.
-__device__ __forceinline__ void quad_transpose(uint32_t (&x)[16], int lane) {
-  const bool q0 = lane & 1, q1 = lane & 2;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    uint32_t* v = x + 4 * g;
-    const uint32_t p0 = quad_xor<1>(v[0]), p1 = quad_xor<1>(v[1]);
-    const uint32_t p2 = quad_xor<1>(v[2]), p3 = quad_xor<1>(v[3]);
-    const uint32_t n0 = q0 ? p1 : v[0], n1 = q0 ? v[1] : p0;
-    const uint32_t n2 = q0 ? p3 : v[2], n3 = q0 ? v[3] : p2;
-    const uint32_t r0 = quad_xor<2>(n0), r1 = quad_xor<2>(n1);
-    const uint32_t r2 = quad_xor<2>(n2), r3 = quad_xor<2>(n3);
-    v[0] = q1 ? r2 : n0;
-    v[1] = q1 ? r3 : n1;
-    v[2] = q1 ? n2 : r0;
-    v[3] = q1 ? n3 : r1;
-  }
+  for (int r = 0; r < 16; ++r) x[r] = buf[lds_slot(TO(lane, r))];
 }
 
 // Position of twiddle-table entry 2^S + o inside stage S's slice of a
-// per-prime LDS plane.  Stage S >= 4 reads entry offsets o whose bits hold the
-// lane group h = lane >> 2 (and, in layout C, q = lane & 3) above bits set by
-// the register index; the permutation moves the lane bits to the bottom, so
-// for every butterfly slot the 64 lanes read one contiguous run of entries
-// (no bank conflicts).  A bijection on [0, 2^S) for every S.
+// per-prime LDS plane.  Stage S >= 4 reads entry offsets o = j >> (10 - S)
+// whose top bits hold lane bits (a = lane & 15 in layout Y; a and h = lane >> 4
+// in layout Z) above bits set by the register index (c); the permutation
+// moves the lane bits to the bottom, so for every butterfly slot the lanes
+// read one contiguous run of entries (no bank conflicts).  A bijection on
+// [0, 2^S) for every S.
 __host__ __device__ __forceinline__ constexpr int tw_perm(int S, int o) {
   return S < 4    ? o
-         : S <= 7 ? (((o & ((1 << (S - 4)) - 1)) << 4) | (o >> (S - 4)))                       // o = h | c
-         : S == 8 ? ((((o >> 2) & 3) << 6) | ((o >> 4) << 2) | (o & 3))                        // o = h | c | q
-                  : ((((o >> 3) & 3) << 7) | ((o & 1) << 6) | ((o >> 5) << 2) | ((o >> 1) & 3));  // o = h | c | q | d
+         : S <= 7 ? (((o & ((1 << (S - 4)) - 1)) << 4) | (o >> (S - 4)))          // o = a | c
+         : S == 8 ? (((o & 3) << 6) | (((o >> 2) & 3) << 4) | ((o >> 4) & 15))      // o = a | h | c (2 bits)
+                  : (((o & 7) << 6) | (((o >> 3) & 3) << 4) | ((o >> 5) & 15));     // o = a | h | c (3 bits)
 }
 
 // Stages 0..3 read the global table (wavefront-uniform: scalar loads), entry
@@ -316,27 +310,27 @@ __device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const
   fwd_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
   fwd_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
   fwd_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
-  wave_transpose1<lay_a, lay_b>(x, buf, lane);
-  fwd_stage1<PR, 4, lay_b, 3>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 5, lay_b, 2>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 6, lay_b, 1>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 7, lay_b, 0>(x, tws, gtw2, lane);
-  quad_transpose(x, lane);  // layout B -> C
-  fwd_stage1<PR, 8, lay_c, 1>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 9, lay_c, 0>(x, tws, gtw2, lane);
+  wave_transpose1<lay_a, lay_y>(x, buf, lane);
+  fwd_stage1<PR, 4, lay_y, 3>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 5, lay_y, 2>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 6, lay_y, 1>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 7, lay_y, 0>(x, tws, gtw2, lane);
+  swap_yz(x);  // layout Y -> Z
+  fwd_stage1<PR, 8, lay_z, 3>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 9, lay_z, 2>(x, tws, gtw2, lane);
 }
 
 template <int PR>
 __device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws,
                                          const uint2* __restrict__ gtw2, int lane) {
-  inv_stage1<PR, 9, lay_c, 0>(x, tws, gtw2, lane);
-  inv_stage1<PR, 8, lay_c, 1>(x, tws, gtw2, lane);
-  quad_transpose(x, lane);  // layout C -> B
-  inv_stage1<PR, 7, lay_b, 0>(x, tws, gtw2, lane);
-  inv_stage1<PR, 6, lay_b, 1>(x, tws, gtw2, lane);
-  inv_stage1<PR, 5, lay_b, 2>(x, tws, gtw2, lane);
-  inv_stage1<PR, 4, lay_b, 3>(x, tws, gtw2, lane);
-  wave_transpose1<lay_b, lay_a>(x, buf, lane);
+  inv_stage1<PR, 9, lay_z, 2>(x, tws, gtw2, lane);
+  inv_stage1<PR, 8, lay_z, 3>(x, tws, gtw2, lane);
+  swap_yz(x);  // layout Z -> Y
+  inv_stage1<PR, 7, lay_y, 0>(x, tws, gtw2, lane);
+  inv_stage1<PR, 6, lay_y, 1>(x, tws, gtw2, lane);
+  inv_stage1<PR, 5, lay_y, 2>(x, tws, gtw2, lane);
+  inv_stage1<PR, 4, lay_y, 3>(x, tws, gtw2, lane);
+  wave_transpose1<lay_y, lay_a>(x, buf, lane);
   inv_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
   inv_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
   inv_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
