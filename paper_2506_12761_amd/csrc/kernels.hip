@@ -342,7 +342,7 @@ template <int ROT>
 __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) void br2_kernel(
     const BrItem* __restrict__ items, uint32_t count, const Tw* __restrict__ tw_fwd) {
   __shared__ uint2 s_tw[2][RING_N];              // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
-  __shared__ uint32_t s_buf[2 * ROT][RING_N];    // per wavefront: transpose scratch, then parked residues
+  __shared__ __align__(16) uint32_t s_buf[2 * ROT][RING_N];  // per wavefront: transpose scratch, then parked residues
   __shared__ uint32_t s_acc[ROT][2][RING_N];     // per rotation: accumulator (A, B), coefficient order
   __shared__ uint16_t s_abar[ROT][CT_n + 1];     // per rotation: modulus-switched input
   for (int e = 16 + threadIdx.x; e < RING_N; e += blockDim.x) {  // stages 4..9 (entries 16..1023)
@@ -507,7 +507,7 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void br4_kernel(
     const BrItem* __restrict__ items, uint32_t count, const Tw* __restrict__ tw_fwd) {
   __shared__ uint2 s_tw[2][RING_N];      // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
-  __shared__ uint32_t s_buf[4][RING_N];  // per wavefront: transpose scratch, then CRT hand-over
+  __shared__ __align__(16) uint32_t s_buf[4][RING_N];  // per wavefront: transpose scratch, then CRT hand-over
   __shared__ uint32_t s_x[4][RING_N];    // per wavefront: partial sum handed to the other half
   __shared__ uint32_t s_acc[2][RING_N];  // accumulator (A, B), coefficient order
   __shared__ uint16_t s_abar[CT_n + 1];  // modulus-switched input

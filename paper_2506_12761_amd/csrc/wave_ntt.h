@@ -242,14 +242,39 @@ struct Prime<1> {
   static constexpr uint32_t P = P2, PINV = P2_INV;
 };
 
-template <int (*FROM)(int, int), int (*TO)(int, int)>
-__device__ __forceinline__ void wave_transpose1(uint32_t (&x)[16], uint32_t* buf, int lane) {
+// LDS word of element j in a single-prime transpose buffer: a bijection on
+// [0, 1024) that puts j and j + 64 (registers 2k and 2k + 1 of one lane in
+// layout A) in one aligned pair of words, so that side of a transpose moves
+// two registers per 64-bit access.  Word bits: 0 = j6, 1..2 = j0..1,
+// 3..5 = (j2..4 xor j7..9), 6 = j5, 7..9 = j7..9.  The 64-bit accesses of each
+// half-wavefront in layout A and the 32-bit accesses of the wavefront in
+// layout Y each touch all 64 banks once.
+__device__ __forceinline__ int lds_slot1(int j) {
+  return ((j >> 6) & 1) | ((j & 3) << 1) | ((((j >> 2) ^ (j >> 7)) & 7) << 3) | (((j >> 5) & 1) << 6) |
+         (j & 0x380);
+}
+
+// Layout A -> Y and Y -> A through the wavefront's 8-byte-aligned LDS buffer.
+__device__ __forceinline__ void transpose_a_to_y(uint32_t (&x)[16], uint32_t* buf, int lane) {
   wave_lds_sync();  // earlier readers of buf are done
 #pragma unroll
-  for (int r = 0; r < 16; ++r) buf[lds_slot(FROM(lane, r))] = x[r];
+  for (int k = 0; k < 8; ++k)
+    *reinterpret_cast<uint2*>(buf + lds_slot1(lay_a(lane, 2 * k))) = make_uint2(x[2 * k], x[2 * k + 1]);
   wave_lds_sync();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = buf[lds_slot(TO(lane, r))];
+  for (int r = 0; r < 16; ++r) x[r] = buf[lds_slot1(lay_y(lane, r))];
+}
+__device__ __forceinline__ void transpose_y_to_a(uint32_t (&x)[16], uint32_t* buf, int lane) {
+  wave_lds_sync();  // earlier readers of buf are done
+#pragma unroll
+  for (int r = 0; r < 16; ++r) buf[lds_slot1(lay_y(lane, r))] = x[r];
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint2 t = *reinterpret_cast<const uint2*>(buf + lds_slot1(lay_a(lane, 2 * k)));
+    x[2 * k] = t.x;
+    x[2 * k + 1] = t.y;
+  }
 }
 
 // Position of twiddle-table entry 2^S + o inside stage S's slice of a
@@ -310,7 +335,7 @@ __device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const
   fwd_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
   fwd_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
   fwd_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
-  wave_transpose1<lay_a, lay_y>(x, buf, lane);
+  transpose_a_to_y(x, buf, lane);
   fwd_stage1<PR, 4, lay_y, 3>(x, tws, gtw2, lane);
   fwd_stage1<PR, 5, lay_y, 2>(x, tws, gtw2, lane);
   fwd_stage1<PR, 6, lay_y, 1>(x, tws, gtw2, lane);
@@ -330,7 +355,7 @@ __device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const
   inv_stage1<PR, 6, lay_y, 1>(x, tws, gtw2, lane);
   inv_stage1<PR, 5, lay_y, 2>(x, tws, gtw2, lane);
   inv_stage1<PR, 4, lay_y, 3>(x, tws, gtw2, lane);
-  wave_transpose1<lay_y, lay_a>(x, buf, lane);
+  transpose_y_to_a(x, buf, lane);
   inv_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
   inv_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
   inv_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
