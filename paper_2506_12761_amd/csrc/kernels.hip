@@ -613,9 +613,12 @@ __global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict
       const int sh = 30 - 2 * j;
 #pragma unroll
       for (int g = 0; g < T; ++g) {
-        const uint32_t d = (a[g] >> sh) & 3u;
-        const uint32_t s0 = d == 0 ? 0u : (d == 1 ? k10 : (d == 2 ? k20 : k30));
-        const uint32_t s1 = d == 0 ? 0u : (d == 1 ? k11 : (d == 2 ? k21 : k31));
+        // Digit d = 2 b1 + b0 selects row d (none for 0).  The digit is the
+        // same for the whole workgroup: two scalar bit tests give the masks
+        // of three selects per word.
+        const bool b0 = (a[g] >> sh) & 1u, b1 = (a[g] >> (sh + 1)) & 1u;
+        const uint32_t s0 = b0 ? (b1 ? k30 : k10) : (b1 ? k20 : 0u);
+        const uint32_t s1 = b0 ? (b1 ? k31 : k11) : (b1 ? k21 : 0u);
         acc[g][0] -= s0;
         acc[g][1] -= s1;
       }
