@@ -78,7 +78,7 @@ WORKLOADS = {
 
 
 def mixed_programs(cells=4096, seed=0x5EED0003):
-    from paper_2506_12761_amd import synth
+    import synth
     coin = synth.bits(synth.stream(seed, "cell_kind"), (cells,))
     n_eq = int(coin.sum())
     return [dict(mode="cov", M=n_eq, l=20, lS=0, d=2), dict(mode="intv", M=cells - n_eq, l=20, lS=0, d=2)]
@@ -105,7 +105,7 @@ def cpu_baseline(seconds: float, threads: int):
     import numpy as np
 
     from oracle import oracle as O
-    from paper_2506_12761_amd import synth
+    import synth
     bk, ksk = synth.uniform_keys(0xB0B)
     keys = O.Keys(np.zeros(630, np.uint32), np.zeros(1024, np.uint32), bk, ksk)
     cts = synth.uniform_ciphertexts(0xB0B, "cpu", (2 * threads, 2))
@@ -154,7 +154,8 @@ def table3_bench(args):
     (Alg. 7 AND chain, Alg. 10 XOR chain), optimized circuits (Alg. 11/12,
     XOR tree) and optimized circuits with 16-input XOR aggregation; synthetic
     uniform data of those shapes; latency per query."""
-    from paper_2506_12761_amd import synth, vlp
+    import synth
+    from paper_2506_12761_amd import vlp
     ctx = vlp.Context(0)
     bk, ksk = synth.uniform_keys(0x5EED0006)
     ks = ctx.load_keys(bk, ksk)
@@ -260,7 +261,9 @@ def serve_bench(args):
     import numpy as np
     import torch
 
-    from paper_2506_12761_amd import synth, vlp
+    import synth
+
+    from paper_2506_12761_amd import vlp
     from paper_2506_12761_amd.serve import GpuExecutor, Request, poisson_arrivals, serve
     ctx = vlp.Context(0)
     keysets = {}
@@ -377,7 +380,9 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2506_12761_amd import synth, vlp
+    import synth
+
+    from paper_2506_12761_amd import vlp
     assert torch.cuda.is_available(), "no HIP device"
     wl = WORKLOADS[args.workload]
     specs = mixed_programs() if wl["programs"] == "mixed" else [dict(p) for p in wl["programs"]]

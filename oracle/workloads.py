@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_2506_12761_amd import synth
+import synth
 
 from . import circuits as C
 from . import oracle as O

@@ -20,5 +20,5 @@ KEY_SEED = 0x5EED0001
 def oracle_keys():
     """One real client key set (seeded), built by the oracle."""
     from oracle import oracle as O
-    from paper_2506_12761_amd import synth
+    import synth
     return O.keygen(synth.key_randomness(KEY_SEED))

@@ -3,7 +3,7 @@ import numpy as np
 
 from oracle import circuits as C
 from oracle import oracle as O
-from paper_2506_12761_amd import synth
+import synth
 
 
 def _enc_int(K, val, l, name, seed):

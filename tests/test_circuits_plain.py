@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import circuits as C
-from paper_2506_12761_amd import synth
+import synth
 
 PB = C.PlainBuilder()
 

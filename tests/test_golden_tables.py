@@ -23,7 +23,8 @@ import pytest
 
 from oracle import circuits as C
 from oracle import oracle as O
-from paper_2506_12761_amd import synth, vlp
+import synth
+from paper_2506_12761_amd import vlp
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GOLDEN = os.path.join(ROOT, "tests", "golden")

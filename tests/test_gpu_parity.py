@@ -4,7 +4,7 @@ import pytest
 
 from oracle import oracle as O
 from oracle import workloads as W
-from paper_2506_12761_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 MU = O.MU

@@ -6,7 +6,7 @@ import pytest
 
 from oracle import oracle as O
 from oracle import workloads as W
-from paper_2506_12761_amd import synth
+import synth
 from paper_2506_12761_amd.serve import GpuExecutor, Request, serve
 
 pytestmark = pytest.mark.gpu

@@ -6,7 +6,7 @@ import pytest
 
 from oracle import oracle as O
 from oracle import server_enc as SE
-from paper_2506_12761_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 

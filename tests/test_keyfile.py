@@ -2,7 +2,8 @@
 import numpy as np
 import pytest
 
-from paper_2506_12761_amd import keyfile, synth
+import synth
+from paper_2506_12761_amd import keyfile
 
 
 def test_round_trip_and_tamper_detection(tmp_path):

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from paper_2506_12761_amd import synth
+import synth
 
 MU = O.MU
 n, N = O.n, O.N

@@ -10,7 +10,7 @@ from oracle import circuits as C
 from oracle import oracle as O
 from oracle import server_enc as SE
 from oracle import workloads as W
-from paper_2506_12761_amd import synth
+import synth
 
 
 def bits_by_format(x: int, l: int) -> list:

@@ -10,7 +10,7 @@ import pytest
 from oracle import circuits as C
 from oracle import oracle as O
 from oracle import workloads as W
-from paper_2506_12761_amd import synth
+import synth
 
 K_MAX = 16  # the largest k the library accepts
 
