@@ -157,6 +157,19 @@ vlp_status vlp_keyswitch(vlp_ctx *ctx, const vlp_keyset *ks, const uint32_t *in_
 vlp_status vlp_gate(vlp_ctx *ctx, const vlp_keyset *ks, vlp_gate_op op, const uint32_t *a_dev, const uint32_t *b_dev,
                     const uint32_t *c_dev, uint32_t *out_dev, size_t B);
 
+/* vlp_gate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same gates, bit for bit, with the intermediate ciphertexts and work items
+ * in a fixed scratch array that the library holds on each device for the
+ * life of the process (8,568,832 B), so the call makes no hipMalloc/hipFree.
+ * B <= 1024 gates per call (VLP_EINVAL above that).  Every call on one
+ * device shares that device's array: calls that overlap in time on the same
+ * device (two contexts or two streams) race and give wrong results; calls
+ * ordered on one stream are safe.  Kernel timing (vlp_profile_enable) does
+ * not cover this call.  Arguments and errors otherwise as vlp_gate. */
+vlp_status vlp_gate_noalloc(vlp_ctx *ctx, const vlp_keyset *ks, vlp_gate_op op, const uint32_t *a_dev,
+                            const uint32_t *b_dev, const uint32_t *c_dev, uint32_t *out_dev, size_t B);
+
 /* Mode-level evaluation of Algorithm 3 for one query.
  *   query_dev : IntV/CoV [d][l_I][631] (coordinate k, bit j LSB first);
  *               IdM [l_I][631]

@@ -52,6 +52,18 @@ struct KsItem {
   uint32_t pad;
 };
 
+// Fixed device scratch of the allocation-free gate call (vlp_gate_noalloc):
+// the sample-extracted outputs of up to 2 blind rotations per gate, then the
+// blind-rotation and key-switching work items, for at most
+// NOALLOC_MAX_GATES gates per call.  One copy per device, in kernels.hip.
+constexpr size_t NOALLOC_MAX_GATES = 1024;
+constexpr size_t NOALLOC_EXT_BYTES = 2 * NOALLOC_MAX_GATES * CT_N * 4;   // multiple of 256
+constexpr size_t NOALLOC_BYTES = NOALLOC_EXT_BYTES + 2 * NOALLOC_MAX_GATES * sizeof(BrItem) +
+                                 NOALLOC_MAX_GATES * sizeof(KsItem);
+// Device address of the current device's copy of that scratch (the HIP error
+// of the lookup; call with the device current).
+int noalloc_scratch_address(void** p);
+
 // Host-side launchers (kernels.hip).  All enqueue on `stream` and return the
 // HIP error of the launch.
 int launch_bk_transform(const uint32_t* bk_coeff, uint32_t* bk_ntt, const uint4* tw_fwd, void* stream);

@@ -775,6 +775,19 @@ __global__ void server_enc_inplace_kernel(uint32_t* ct, size_t count, const int6
 }
 
 // ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free gate call.  Each device holds its own
+// copy for the life of the process.  On the host, `scratch` names a host-side
+// stand-in, not device memory: host code uses only the address that
+// noalloc_scratch_address() returns for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
+int noalloc_scratch_address(void** p) {
+  *p = nullptr;
+  return (int)hipGetSymbolAddress(p, HIP_SYMBOL(scratch));
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }

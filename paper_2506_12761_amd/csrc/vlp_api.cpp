@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,8 @@ struct vlp_ctx {
   // Grow-only scratch for the elementwise calls.
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  // This device's fixed scratch for vlp_gate_noalloc (device address).
+  void* noalloc = nullptr;
   int live_keysets = 0, live_programs = 0;
   std::list<vlp_program*> eval_cache;  // programs made by vlp_evaluate, most recent first
   // Kernel timing (vlp_profile_enable).
@@ -129,6 +132,25 @@ vlp_status ensure_scratch(vlp_ctx* ctx, size_t bytes) {
   if (st != VLP_OK) return st;
   ctx->scratch_bytes = want;
   return VLP_OK;
+}
+
+// Device addresses of the fixed no-allocation scratch, one per device, looked
+// up once (with that device current) by the first context made on it.
+std::mutex g_noalloc_mu;
+std::vector<void*> g_noalloc_addr;
+
+hipError_t noalloc_address_for(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if ((size_t)device >= g_noalloc_addr.size()) g_noalloc_addr.resize((size_t)device + 1, nullptr);
+  if (!g_noalloc_addr[(size_t)device]) {
+    void* p = nullptr;
+    const hipError_t e = (hipError_t)noalloc_scratch_address(&p);
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_addr[(size_t)device] = p;
+  }
+  *out = g_noalloc_addr[(size_t)device];
+  return hipSuccess;
 }
 
 bool params_ok(const vlp_params* p) {
@@ -296,6 +318,10 @@ extern "C" vlp_status vlp_ctx_create(vlp_ctx** out, const vlp_params* p, int dev
       ctx->own_stream = e == hipSuccess;
     }
   }
+  if (e == hipSuccess) {
+    e = noalloc_address_for(device, &ctx->noalloc);
+    if (e != hipSuccess && ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  }
   if (e != hipSuccess) {
     g_create_err = std::string("HIP set-up failed: ") + hipGetErrorString(e);
     delete ctx;
@@ -455,9 +481,11 @@ extern "C" vlp_status vlp_keyswitch(vlp_ctx* ctx, const vlp_keyset* ks, const ui
   return VLP_OK;
 }
 
-extern "C" vlp_status vlp_gate(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const uint32_t* a_dev,
-                               const uint32_t* b_dev, const uint32_t* c_dev, uint32_t* out_dev, size_t B) {
-  if (!ctx) return VLP_EINVAL;
+namespace {
+
+// Argument checks shared by the two gate calls; VLP_OK when the call may run.
+vlp_status gate_args(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const uint32_t* a_dev, const uint32_t* b_dev,
+                     const uint32_t* c_dev, uint32_t* out_dev, size_t B) {
   if (op < VLP_AND || op > VLP_MUX) return fail(ctx, VLP_EINVAL, "unknown gate op %d", (int)op);
   if (B == 0) return VLP_OK;
   if (!ks || ks->ctx != ctx || !a_dev || !out_dev) return fail(ctx, VLP_EINVAL, "null or foreign argument");
@@ -468,18 +496,27 @@ extern "C" vlp_status vlp_gate(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op o
   if (ranges_overlap(a_dev, nb, out_dev, nb) || ranges_overlap(b_dev, nb, out_dev, nb) ||
       ranges_overlap(c_dev, nb, out_dev, nb))
     return fail(ctx, VLP_EINVAL, "output overlaps an input");
-  if (op == VLP_NOT) {
-    LAUNCHCHECK(ctx, launch_negate(a_dev, out_dev, B * CT_n, ctx->stream));
-    return VLP_OK;
-  }
+  return VLP_OK;
+}
+
+// Bytes of scratch a bootstrapped gate call over B gates lays out from `base`:
+// sample-extracted outputs (one or two per gate), then the blind-rotation and
+// key-switching items.
+constexpr size_t gate_scratch_bytes(vlp_gate_op op, size_t B) {
+  return (((op == VLP_MUX ? 2 * B : B) * CT_N * 4 + 255) & ~(size_t)255) + (op == VLP_MUX ? 2 * B : B) * sizeof(BrItem) +
+         B * sizeof(KsItem);
+}
+static_assert(gate_scratch_bytes(VLP_MUX, NOALLOC_MAX_GATES) <= NOALLOC_BYTES, "fixed scratch too small");
+
+// Enqueues B bootstrapped gates (op != NOT) with their scratch at `base`.
+// Kernel timing (vlp_profile_enable) only when `timed`.
+vlp_status gate_run(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const uint32_t* a_dev, const uint32_t* b_dev,
+                    const uint32_t* c_dev, uint32_t* out_dev, size_t B, void* base, bool timed) {
   const size_t units = op == VLP_MUX ? 2 * B : B;
   const size_t ext_bytes = (units * CT_N * 4 + 255) & ~(size_t)255;
-  const size_t br_bytes = units * sizeof(BrItem), ks_bytes = B * sizeof(KsItem);
-  vlp_status st = ensure_scratch(ctx, ext_bytes + br_bytes + ks_bytes + 256);
-  if (st != VLP_OK) return st;
-  uint32_t* ext = (uint32_t*)ctx->scratch;
-  BrItem* bri = (BrItem*)((char*)ctx->scratch + ext_bytes);
-  KsItem* ksi = (KsItem*)((char*)bri + br_bytes);
+  uint32_t* ext = (uint32_t*)base;
+  BrItem* bri = (BrItem*)((char*)base + ext_bytes);
+  KsItem* ksi = (KsItem*)((char*)bri + units * sizeof(BrItem));
   int32_t ca, cb;
   uint32_t cst;
   gate_coeffs((uint8_t)op, &ca, &cb, &cst);
@@ -487,11 +524,47 @@ extern "C" vlp_status vlp_gate(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op o
   if (op == VLP_MUX)
     LAUNCHCHECK(ctx, launch_make_br_items(bri + B, (uint32_t)B, a_dev, c_dev, -1, 1, 0u - MU, MU, ext + B * CT_N,
                                           ks->bk_ntt, ctx->stream));
-  LAUNCHCHECK(ctx, timed_br(ctx, bri, (uint32_t)units));
-  LAUNCHCHECK(ctx, launch_make_ks_items(ksi, (uint32_t)B, ext, op == VLP_MUX ? ext + B * CT_N : nullptr,
-                                        op == VLP_MUX ? MU : 0u, out_dev, ks->ksk, ctx->stream));
-  LAUNCHCHECK(ctx, timed_ks(ctx, ksi, (uint32_t)B, ks->ksk));
+  const bool prof = ctx->prof;
+  ctx->prof = prof && timed;
+  int e = timed_br(ctx, bri, (uint32_t)units);
+  if (e == 0)
+    e = launch_make_ks_items(ksi, (uint32_t)B, ext, op == VLP_MUX ? ext + B * CT_N : nullptr, op == VLP_MUX ? MU : 0u,
+                             out_dev, ks->ksk, ctx->stream);
+  if (e == 0) e = timed_ks(ctx, ksi, (uint32_t)B, ks->ksk);
+  ctx->prof = prof;
+  if (e != 0) return fail(ctx, VLP_EHIP, "gate launch: %s", hipGetErrorString((hipError_t)e));
   return VLP_OK;
+}
+
+}  // namespace
+
+extern "C" vlp_status vlp_gate(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const uint32_t* a_dev,
+                               const uint32_t* b_dev, const uint32_t* c_dev, uint32_t* out_dev, size_t B) {
+  if (!ctx) return VLP_EINVAL;
+  vlp_status st = gate_args(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B);
+  if (st != VLP_OK || B == 0) return st;
+  if (op == VLP_NOT) {
+    LAUNCHCHECK(ctx, launch_negate(a_dev, out_dev, B * CT_n, ctx->stream));
+    return VLP_OK;
+  }
+  st = ensure_scratch(ctx, gate_scratch_bytes(op, B) + 256);
+  if (st != VLP_OK) return st;
+  return gate_run(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B, ctx->scratch, true);
+}
+
+extern "C" vlp_status vlp_gate_noalloc(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const uint32_t* a_dev,
+                                       const uint32_t* b_dev, const uint32_t* c_dev, uint32_t* out_dev, size_t B) {
+  if (!ctx) return VLP_EINVAL;
+  vlp_status st = gate_args(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B);
+  if (st != VLP_OK || B == 0) return st;
+  if (B > NOALLOC_MAX_GATES)
+    return fail(ctx, VLP_EINVAL, "B = %zu exceeds the %zu gates the fixed scratch holds", B, NOALLOC_MAX_GATES);
+  if (op == VLP_NOT) {
+    LAUNCHCHECK(ctx, launch_negate(a_dev, out_dev, B * CT_n, ctx->stream));
+    return VLP_OK;
+  }
+  if (!ctx->noalloc) return fail(ctx, VLP_EHIP, "no fixed scratch on device %d", ctx->device);
+  return gate_run(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B, ctx->noalloc, false);
 }
 
 // ---------------------------------------------------------------------------

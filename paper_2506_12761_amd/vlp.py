@@ -29,7 +29,8 @@ MU = 1 << 29
 # Every entry point of include/vlp.h.
 EXPORTS = [
     "vlp_version", "vlp_default_params", "vlp_ctx_create", "vlp_ctx_destroy", "vlp_last_error", "vlp_mem_info",
-    "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_evaluate", "vlp_server_encrypt",
+    "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_gate_noalloc",
+    "vlp_evaluate", "vlp_server_encrypt",
     "vlp_program_create", "vlp_program_reset", "vlp_step", "vlp_program_run", "vlp_program_counts",
     "vlp_plan_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
     "vlp_profile_enable", "vlp_profile_read", "vlp_measure_modmul_peak",
@@ -85,6 +86,7 @@ def lib():
             "vlp_bootstrap": (ctypes.c_int, [vp, vp, vp, vp, u32, sz]),
             "vlp_keyswitch": (ctypes.c_int, [vp, vp, vp, vp, sz]),
             "vlp_gate": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp, vp, vp, sz]),
+            "vlp_gate_noalloc": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp, vp, vp, sz]),
             "vlp_evaluate": (ctypes.c_int, [vp, vp, P(vlp_shape), vp, vp, vp, vp, vp]),
             "vlp_server_encrypt": (ctypes.c_int, [vp, P(vlp_shape), vp, vp, vp, vp, vp, vp]),
             "vlp_program_create": (ctypes.c_int, [vp, vp, P(vlp_shape), vp, vp, vp, vp, vp, P(vp)]),
@@ -186,6 +188,12 @@ def vlp_gate(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B: int) -> None:
     if isinstance(op, str):
         op = GATES[op]
     _check(ctx, lib().vlp_gate(ctx, ks, op, _ptr(a_dev), _ptr(b_dev), _ptr(c_dev), _ptr(out_dev), B))
+
+
+def vlp_gate_noalloc(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B: int) -> None:
+    if isinstance(op, str):
+        op = GATES[op]
+    _check(ctx, lib().vlp_gate_noalloc(ctx, ks, op, _ptr(a_dev), _ptr(b_dev), _ptr(c_dev), _ptr(out_dev), B))
 
 
 def make_shape(mode, M, l_I, l_S=0, d=2, optimized=True, agg_k=0) -> vlp_shape:
