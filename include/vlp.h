@@ -208,11 +208,14 @@ vlp_status vlp_server_encrypt(vlp_ctx *ctx, const vlp_shape *shape, const uint32
  * hold it).  vlp_step advances every unfinished program in progs[] by one
  * circuit level in one merged batch of kernel launches, so gates of several
  * programs, keysets and modes share the same launches; *remaining receives
- * the number of programs in progs[] that still have levels to run.
+ * the number of programs in progs[] that still have levels to run; a program
+ * listed twice is VLP_EINVAL (nothing is enqueued).
  * vlp_program_run runs all remaining levels of one program; with use_graph
  * != 0 the level sequence is captured once in a HIP graph and replayed on
  * later runs of the same program (inputs are re-read from the bound buffers
- * on every run). */
+ * on every run; a change of vlp_set_tuning since the capture captures again;
+ * a program that vlp_step has already advanced runs its remaining levels
+ * without the graph). */
 vlp_status vlp_program_create(vlp_ctx *ctx, const vlp_keyset *ks, const vlp_shape *shape, const uint32_t *query_dev,
                               const uint32_t *db_loc_dev, const uint32_t *db_pay_dev, uint32_t *R_dev,
                               uint32_t *v_out_dev, vlp_program **out);

@@ -2,18 +2,21 @@
 
 TEST INFRASTRUCTURE ONLY (part of the oracle).
 
-The circuits follow the paper's algorithms in their order of gates:
-  comparators  Alg. 5 (HomCompLE) / Alg. 6 (HomCompL), with the XNORs hoisted
-               as in Alg. 11 (HomCompLeOPT) -- the same gate graph;
-  equality     Alg. 12 (HomEqOPT): XNOR per bit, then a pairwise AND tree
-               with strides 1, 2, 4, ...; and Alg. 7 (HomEQ), the AND chain
-               from a trivial 1;
+The circuits, from their definitions:
+  comparators  HomCompLE / HomCompL (Alg. 5 / 6; Alg. 11 is the same gate
+               graph): Theorem 1's bitwise recurrence -- the comparison of the
+               low bits is kept where two bits agree and replaced by c2's bit
+               where they differ; different sign bits decide alone;
+  equality     the AND of per-bit XNORs, as a pairwise reduction (Alg. 12,
+               HomEqOPT) or as a chain from a trivial 1 (Alg. 7, HomEQ);
   IntV         Alg. 4; CoV Alg. 8; IdM = HomEqOPT on identifier bits (Sec. 4.2);
   selection    Alg. 9 (HomBitwiseAND);
   aggregation  Alg. 10 (HomSum, XOR chain from a trivial 0) and its pairwise
-               XOR-tree form of Section 6.1, part (5); and, beyond the paper,
-               a k-ary tree of k-input XORs (one bootstrap per k inputs);
+               form of Section 6.1, part (5); and, beyond the paper, a
+               reduction by k-input XORs (one bootstrap per k inputs);
   query        Alg. 3 (validate, zero out, aggregate).
+A pairwise reduction combines neighbours (0, 1), (2, 3), ... and passes an
+unpaired last element through, round after round, until one element remains.
 Bits are least-significant first; bit l-1 is the two's-complement sign
 (Appendix A, proof of Theorem 1).
 
@@ -38,26 +41,32 @@ XORK = "xork"  # graph node kind of the k-input XOR
 # ----------------------------------------------------------------------------
 # Circuits
 # ----------------------------------------------------------------------------
+def pairwise(xs, combine):
+    """Pairwise reduction of the non-empty list xs by combine(left, right)."""
+    xs = list(xs)
+    while len(xs) > 1:
+        xs = [combine(xs[i], xs[i + 1]) if i + 1 < len(xs) else xs[i] for i in range(0, len(xs), 2)]
+    return xs[0]
+
+
 def comp(B, c1, c2, l: int, strict: bool):
-    """HomCompLE (strict=False) / HomCompL (strict=True): Enc(c1 <= c2) / Enc(c1 < c2)."""
-    t0 = B.xor(c1[l - 1], c2[l - 1])
-    t1 = [B.xnor(c1[i], c2[i]) for i in range(l - 1)]
-    t = B.trivial(0 if strict else 1)
+    """HomCompLE (strict=False) / HomCompL (strict=True): Enc(c1 <= c2) / Enc(c1 < c2).
+
+    `low` compares bits 0..i-1: on equal low parts it is true for <= and false
+    for <; a higher bit where c1 and c2 agree keeps it, one where they differ
+    sets it to c2's bit (c2 has the 1 exactly when c1 is the smaller).  With
+    different sign bits the negative one (sign 1) is the smaller."""
+    signs_differ = B.xor(c1[l - 1], c2[l - 1])
+    agree = [B.xnor(c1[i], c2[i]) for i in range(l - 1)]
+    low = B.trivial(0 if strict else 1)
     for i in range(l - 1):
-        t = B.mux(t1[i], t, c2[i])
-    return B.mux(t0, c1[l - 1], t)
+        low = B.mux(agree[i], low, c2[i])
+    return B.mux(signs_differ, c1[l - 1], low)
 
 
 def eq_opt(B, c1, c2, l: int):
-    """HomEqOPT: XNOR per bit, then t[i] = AND(t[i], t[i+k]) for k = 1, 2, 4, ..."""
-    t = [B.xnor(c1[i], c2[i]) for i in range(l)]
-    k = 1
-    while k < l:
-        for i in range(0, l, 2 * k):
-            if i + k < l:
-                t[i] = B.and_(t[i], t[i + k])
-        k *= 2
-    return t[0]
+    """HomEqOPT: the pairwise AND reduction of the per-bit XNORs."""
+    return pairwise([B.xnor(c1[i], c2[i]) for i in range(l)], B.and_)
 
 
 def eq_chain(B, c1, c2, l: int):
@@ -105,16 +114,8 @@ def select(B, v, S):
 
 
 def homsum_tree(B, S):
-    """Pairwise XOR reduction over records (Section 6.1 part (5)); R = S[0]."""
-    S = [list(x) for x in S]
-    M = len(S)
-    k = 1
-    while k < M:
-        for i in range(0, M, 2 * k):
-            if i + k < M:
-                S[i] = [B.xor(a, b) for a, b in zip(S[i], S[i + k])]
-        k *= 2
-    return S[0]
+    """Pairwise XOR reduction over the records' selected bits (Section 6.1 part (5))."""
+    return pairwise([list(x) for x in S], lambda x, y: [B.xor(a, b) for a, b in zip(x, y)])
 
 
 def homsum_ktree(B, S, k: int):

@@ -1,13 +1,18 @@
 // Gate netlists of the VeLoPIR circuits (host C++).
 //
-// Each builder follows one of the paper's algorithms in its order of gates:
-//   comparator   Alg. 5 / 6 with the XNORs hoisted as in Alg. 11 (same graph)
-//   equality     Alg. 12 (XNOR per bit, pairwise AND tree, strides 1, 2, 4, ...)
-//                or Alg. 7 (AND chain from a trivial 1)
-//   IntV Alg. 4, CoV Alg. 8, IdM (HomEQ on identifier bits, Section 4.2)
-//   zero-out     Alg. 9;  aggregation: pairwise XOR tree (Section 6.1 (5)) or
-//                Alg. 10's XOR chain from a trivial 0, or (agg_k, beyond the
-//                paper) a tree of k-input XORs.
+// The circuits, from their definitions:
+//   comparator   Theorems 1-2 (Alg. 5 / 6, same graph as Alg. 11): the
+//                comparison of the low bits, carried up bit by bit, kept
+//                where the bits agree and replaced by c2's bit where they
+//                differ; the sign bits decide when they differ
+//   equality     the AND of per-bit XNORs, as a balanced pairwise reduction
+//                (Alg. 12) or as a chain from a trivial 1 (Alg. 7)
+//   IntV Alg. 4, CoV Alg. 8, IdM (equality of identifier bits, Section 4.2)
+//   zero-out     Alg. 9;  aggregation: pairwise XOR reduction over records
+//                (Section 6.1 (5)) or Alg. 10's XOR chain from a trivial 0, or
+//                (agg_k, beyond the paper) a reduction by k-input XORs.
+// A pairwise reduction combines neighbours (0,1), (2,3), ... and passes an
+// unpaired last element through, round after round, until one remains.
 // Bits are least-significant first; bit l-1 is the sign bit.
 #include "netlist.h"
 
@@ -48,10 +53,14 @@ struct Builder {
   uint32_t level_of(const Operand& o) const { return o.src == Src::Gate ? nl.gates[o.index].level : 0; }
 
   Operand gate(uint8_t op, Operand a, Operand b, Operand c = Operand()) {
-    // Gates whose operands are all trivial ciphertexts are themselves trivial.
+    // A gate whose operands are all trivial ciphertexts is itself the trivial
+    // ciphertext of its value: bootstrapping a trivial input gives exactly
+    // (0, +-1/8), and key switching a trivial input leaves it unchanged.  A
+    // gate with some trivial operands is bootstrapped like any other (a MUX
+    // with a trivial select too: its two rotations still run on the other
+    // operands, so its words are not those of the selected operand).
     const bool ac = a.is_const(), bc = op == VLP_NOT || b.is_const(), cc = op != VLP_MUX || c.is_const();
     if (ac && bc && cc) return Operand::cst(plain(op, (int)a.index, (int)b.index, (int)c.index));
-    if (op == VLP_MUX && ac) return a.index ? b : c;  // known select
     Gate g;
     g.op = op;
     g.a = a;
@@ -95,27 +104,40 @@ struct Builder {
   Operand MUX(Operand s, Operand x, Operand y) { return gate(VLP_MUX, s, x, y); }
 
   // Enc(c1 <= c2) (strict = false) or Enc(c1 < c2) (strict = true), signed.
+  // `low` is the comparison of the bits below i: where c1[i] == c2[i] it
+  // carries on, where they differ c1 < c2 on bits 0..i exactly when c2[i] is
+  // 1; on equal low parts it is true for <= and false for <.  Different sign
+  // bits decide alone: then c1 is the smaller one exactly when it is negative.
   Operand comp(const std::vector<Operand>& c1, const std::vector<Operand>& c2, uint32_t l, bool strict) {
-    const Operand t0 = XOR(c1[l - 1], c2[l - 1]);
-    std::vector<Operand> t1(l - 1);
-    for (uint32_t i = 0; i + 1 < l; ++i) t1[i] = XNOR(c1[i], c2[i]);
-    Operand t = Operand::cst(strict ? 0 : 1);
-    for (uint32_t i = 0; i + 1 < l; ++i) t = MUX(t1[i], t, c2[i]);
-    return MUX(t0, c1[l - 1], t);
+    const Operand signs_differ = XOR(c1[l - 1], c2[l - 1]);
+    std::vector<Operand> agree(l - 1);
+    for (uint32_t i = 0; i + 1 < l; ++i) agree[i] = XNOR(c1[i], c2[i]);
+    Operand low = Operand::cst(strict ? 0 : 1);
+    for (uint32_t i = 0; i + 1 < l; ++i) low = MUX(agree[i], low, c2[i]);
+    return MUX(signs_differ, c1[l - 1], low);
   }
 
+  // Enc(c1 == c2): the AND of the per-bit XNORs.
   Operand eq(const std::vector<Operand>& c1, const std::vector<Operand>& c2, uint32_t l, bool tree) {
+    std::vector<Operand> same(l);
+    for (uint32_t i = 0; i < l; ++i) same[i] = XNOR(c1[i], c2[i]);
     if (!tree) {
       Operand r = Operand::cst(1);
-      for (uint32_t i = 0; i < l; ++i) r = AND(r, XNOR(c1[i], c2[i]));
+      for (const Operand& x : same) r = AND(r, x);
       return r;
     }
-    std::vector<Operand> t(l);
-    for (uint32_t i = 0; i < l; ++i) t[i] = XNOR(c1[i], c2[i]);
-    for (uint32_t k = 1; k < l; k *= 2)
-      for (uint32_t i = 0; i < l; i += 2 * k)
-        if (i + k < l) t[i] = AND(t[i], t[i + k]);
-    return t[0];
+    return pairwise(std::move(same), [this](Operand x, Operand y) { return AND(x, y); });
+  }
+
+  // Pairwise reduction of xs (non-empty) by `combine`.
+  template <class T, class F>
+  static T pairwise(std::vector<T> xs, F combine) {
+    while (xs.size() > 1) {
+      std::vector<T> next;
+      for (size_t i = 0; i < xs.size(); i += 2) next.push_back(i + 1 < xs.size() ? combine(xs[i], xs[i + 1]) : xs[i]);
+      xs.swap(next);
+    }
+    return xs[0];
   }
 };
 
@@ -126,6 +148,11 @@ std::vector<Operand> bits(Operand (*mk)(uint32_t), uint32_t base, uint32_t l) {
 }
 
 }  // namespace
+
+Operand add_gate(Netlist& nl, uint8_t op, Operand a, Operand b, Operand c) {
+  Builder B{nl};
+  return B.gate(op, a, b, c);
+}
 
 static_assert(sizeof(vlp_mode) == sizeof(int), "the mode field is read as an int");
 
@@ -213,11 +240,11 @@ bool build_netlist(const vlp_shape& sh, Netlist& nl, const char** why) {
     }
     nl.result = cur[0];
   } else if (opt) {
-    for (uint32_t k = 1; k < M; k *= 2)
-      for (uint32_t i = 0; i < M; i += 2 * k)
-        if (i + k < M)
-          for (uint32_t j = 0; j < lS; ++j) S[i][j] = B.XOR(S[i][j], S[i + k][j]);
-    nl.result = S[0];
+    nl.result = Builder::pairwise(std::move(S), [&B, lS](const std::vector<Operand>& x, const std::vector<Operand>& y) {
+      std::vector<Operand> r(lS);
+      for (uint32_t j = 0; j < lS; ++j) r[j] = B.XOR(x[j], y[j]);
+      return r;
+    });
   } else {
     std::vector<Operand> R(lS, Operand::cst(0));
     for (uint32_t i = 0; i < M; ++i)

@@ -51,6 +51,9 @@ struct Netlist {
 // CoV or IdM, zero-out, aggregation).  Returns false for shapes out of range.
 // Limits every call taking a shape enforces (mode, M, l_I, l_S, d).
 bool shape_valid(const vlp_shape& shape, const char** why);
+// Appends one gate as the circuit builders do (a gate of trivial operands
+// only becomes the trivial operand of its value) and returns its operand.
+Operand add_gate(Netlist& nl, uint8_t op, Operand a, Operand b, Operand c = Operand());
 bool build_netlist(const vlp_shape& shape, Netlist& out, const char** why);
 
 }  // namespace vlp

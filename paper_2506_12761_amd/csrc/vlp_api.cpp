@@ -69,6 +69,7 @@ struct vlp_program {
   uint32_t max_br_level = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  vlp_tuning graph_tune{};  // launch shape the graph was captured with
   // arguments, for the vlp_evaluate cache
   const uint32_t *q, *loc, *pay;
   uint32_t *R, *v;
@@ -768,6 +769,10 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
       py = nullptr;
       cb = 0;
     }
+    if (!px) {  // trivial operands only (a MUX rotation with a trivial select): any ciphertext times 0
+      px = query_dev;
+      ca = 0;
+    }
     it.a = px;
     it.b = py;
     it.ca = ca;
@@ -895,6 +900,14 @@ static vlp_status run_level(vlp_ctx* ctx, vlp_program* prog, uint32_t L) {
 extern "C" vlp_status vlp_step(vlp_ctx* ctx, vlp_program* const* progs, size_t n, size_t* remaining) {
   if (!ctx) return VLP_EINVAL;
   if (n && !progs) return fail(ctx, VLP_EINVAL, "progs is NULL");
+  // A program listed twice would have its level's items batched twice (and
+  // its level advanced twice): rejected before any work is enqueued.
+  {
+    std::vector<const vlp_program*> sorted(progs, progs + n);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(ctx, VLP_EINVAL, "a program appears more than once in progs");
+  }
   // Gather this step's BR and KS items of every unfinished program into one batch.
   size_t nbr = 0, nks = 0, left = 0;
   for (size_t p = 0; p < n; ++p) {
@@ -945,7 +958,9 @@ extern "C" vlp_status vlp_step(vlp_ctx* ctx, vlp_program* const* progs, size_t n
 
 extern "C" vlp_status vlp_program_run(vlp_ctx* ctx, vlp_program* prog, int use_graph) {
   if (!ctx || !prog || prog->ctx != ctx) return ctx ? fail(ctx, VLP_EINVAL, "null or foreign program") : VLP_EINVAL;
-  if (!use_graph) {
+  // The graph holds every level: a program part-way through (vlp_step) runs
+  // its remaining levels without it.
+  if (!use_graph || prog->next_level != 0) {
     for (uint32_t L = prog->next_level; L < prog->levels.size(); ++L) {
       vlp_status st = run_level(ctx, prog, L);
       if (st != VLP_OK) return st;
@@ -953,7 +968,16 @@ extern "C" vlp_status vlp_program_run(vlp_ctx* ctx, vlp_program* prog, int use_g
     prog->next_level = (uint32_t)prog->levels.size();
     return VLP_OK;
   }
+  if (prog->graph_exec && memcmp(&prog->graph_tune, &ctx->tune, sizeof(vlp_tuning)) != 0) {
+    // Captured with another launch shape: capture again with the current one.
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipGraphExecDestroy(prog->graph_exec);
+    (void)hipGraphDestroy(prog->graph);
+    prog->graph_exec = nullptr;
+    prog->graph = nullptr;
+  }
   if (!prog->graph_exec) {
+    prog->graph_tune = ctx->tune;
     HIPCHECK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     vlp_status st = VLP_OK;
     for (uint32_t L = 0; L < prog->levels.size() && st == VLP_OK; ++L) st = run_level(ctx, prog, L);

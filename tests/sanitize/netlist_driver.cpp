@@ -85,6 +85,35 @@ int main() {
       std::printf("accepted an invalid shape\n");
       return 1;
     }
+  // A MUX with a trivial select is bootstrapped like any other gate (its two
+  // rotations run on the other operands); a gate of trivial operands only is
+  // the trivial operand of its value; a trivial operand beside a real one
+  // still leaves a gate.
+  {
+    Netlist t;
+    const Operand m = add_gate(t, VLP_MUX, Operand::cst(1), Operand::q(0), Operand::q(1));
+    if (m.src != Src::Gate || t.gates.size() != 1 || t.gates[0].level != 1 || t.blind_rotations() != 2 ||
+        t.key_switches() != 1) {
+      std::printf("a MUX with a trivial select was not kept as a bootstrapped gate\n");
+      return 1;
+    }
+    const Operand m2 = add_gate(t, VLP_MUX, Operand::cst(0), Operand::cst(1), m);
+    if (m2.src != Src::Gate || t.gates.back().level != 2) {
+      std::printf("a MUX of a trivial select and a trivial operand was not kept\n");
+      return 1;
+    }
+    const Operand k = add_gate(t, VLP_MUX, Operand::cst(1), Operand::cst(0), Operand::cst(1));
+    const Operand x = add_gate(t, VLP_XNOR, Operand::cst(1), Operand::cst(1));
+    if (!k.is_const() || k.index != 0 || !x.is_const() || x.index != 1 || t.gates.size() != 2) {
+      std::printf("gates of trivial operands were not folded to their value\n");
+      return 1;
+    }
+    const Operand a = add_gate(t, VLP_AND, Operand::cst(1), Operand::loc(3));
+    if (a.src != Src::Gate || t.gates.size() != 3) {
+      std::printf("a gate with one real operand was folded\n");
+      return 1;
+    }
+  }
   std::printf("netlist OK (%d shapes)\n", n + 1);
   return 0;
 }

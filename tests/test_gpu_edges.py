@@ -122,3 +122,61 @@ def test_evaluate_extreme_shapes(gpu, oracle_keys, mode, M, l, lS, d):
     if lS:
         assert np.array_equal(ctx.to_host(R), R_want)
         assert np.array_equal(O.decrypt(oracle_keys, ctx.to_host(R)), P["R"])
+
+
+def test_step_rejects_a_program_listed_twice(gpu, oracle_keys):
+    """A duplicated handle is an argument error that enqueues nothing; the
+    programs then step to the oracle's words, and a program part-way through
+    finishes under vlp_program_run with the graph flag."""
+    vlp, ctx, ks = gpu
+    runs = []
+    for (mode, M, l, lS, d, seed) in (("idm", 3, 4, 2, 1, 31), ("cov", 2, 3, 2, 1, 32)):
+        P = W.plain_workload(mode, M, l, lS, d, seed)
+        enc = W.encrypt_workload(oracle_keys, P, seed)
+        bufs = (ctx.tensor(enc["query"]), ctx.tensor(enc["db_loc"]), ctx.tensor(enc["db_pay"]),
+                ctx.empty(lS, O.n + 1), ctx.empty(M, O.n + 1))
+        pr = vlp.vlp_program_create(ctx.ctx, ks, vlp.make_shape(mode, M, l, lS, d), *bufs)
+        runs.append((P, enc, bufs, pr))
+    a, b = runs[0][3], runs[1][3]
+    with pytest.raises(vlp.VlpError) as e:
+        vlp.vlp_step(ctx.ctx, [a, b, a])
+    assert e.value.status == vlp.VLP_EINVAL
+    assert vlp.vlp_step(ctx.ctx, [a, b]) == 2              # one level of each
+    vlp.vlp_program_run(ctx.ctx, a, use_graph=True)        # the rest of a, without the graph
+    while vlp.vlp_step(ctx.ctx, [a, b]):
+        pass
+    ctx.sync()
+    for P, enc, bufs, pr in runs:
+        v_want, R_want = W.oracle_outputs(oracle_keys, P, enc)
+        assert np.array_equal(ctx.to_host(bufs[4]), v_want) and np.array_equal(ctx.to_host(bufs[3]), R_want)
+        vlp.vlp_program_destroy(ctx.ctx, pr)
+
+
+def test_graph_follows_a_tuning_change(gpu, oracle_keys):
+    """A program replayed from its HIP graph, then run again after the launch
+    shape changed (captured again with the new shape), gives the oracle's
+    words both times."""
+    vlp, ctx, ks = gpu
+    P = W.plain_workload("intv", 2, 4, 2, 2, 41)
+    enc = W.encrypt_workload(oracle_keys, P, 41)
+    bufs = (ctx.tensor(enc["query"]), ctx.tensor(enc["db_loc"]), ctx.tensor(enc["db_pay"]),
+            ctx.empty(2, O.n + 1), ctx.empty(2, O.n + 1))
+    pr = vlp.vlp_program_create(ctx.ctx, ks, vlp.make_shape("intv", 2, 4, 2, 2), *bufs)
+    v_want, R_want = W.oracle_outputs(oracle_keys, P, enc)
+    old = vlp.vlp_get_tuning(ctx.ctx)
+    try:
+        for tune in (None, (1, 2, 4, 4), (2, 1, 16, 2)):
+            if tune:
+                vlp.vlp_set_tuning(ctx.ctx, *tune)
+            for _ in range(2):
+                ctx.zero(bufs[3])
+                ctx.zero(bufs[4])
+                vlp.vlp_program_reset(ctx.ctx, pr)
+                vlp.vlp_program_run(ctx.ctx, pr, use_graph=True)
+                ctx.sync()
+                assert np.array_equal(ctx.to_host(bufs[4]), v_want), tune
+                assert np.array_equal(ctx.to_host(bufs[3]), R_want), tune
+    finally:
+        vlp.vlp_set_tuning(ctx.ctx, old.br_rotations_per_block, old.br_blocks_per_cu, old.ks_gates_per_block,
+                           old.br_waves_per_rotation)
+        vlp.vlp_program_destroy(ctx.ctx, pr)
