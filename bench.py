@@ -53,7 +53,7 @@ PEAK_MODMUL = VALU_LANE_OPS / (OPS_PER_RESIDUE_BUTTERFLY * RESIDUES_PER_MODMUL) 
 # (their sha256 prefix) and the launch shape it was measured with.
 TRAFFIC_MEASURED = {"kernel_sha": "add300b5915d5b9c", "bytes_per_launch": 5.03574e+08,
                     "launch": {"br_waves_per_rotation": 0, "br_rotations_per_block": 4, "br_blocks_per_cu": 1,
-                               "ks_gates_per_block": 8}}
+                               "ks_gates_per_block": 512}}
 KERNEL_SOURCES = ("kernels.hip", "wave_ntt.h", "rns.h", "vlp_api.cpp")
 
 
@@ -75,6 +75,82 @@ WORKLOADS = {
     "interval-8bit": dict(label="one 8-bit value against one interval (49 bootstraps)",
                           programs=[dict(mode="intv", M=1, l=8, lS=0, d=1)]),
 }
+
+
+# The identifier-match workload reported beside the main line: one full query
+# over 65,536 records (32-bit identifiers, 64 payload bits, pairwise XOR tree).
+CONFIG4 = dict(mode="idm", M=65536, l=32, lS=64, d=1)
+
+
+def device_inputs(ctx, spec, seed):
+    """Query, database and output buffers of one program, the ciphertexts as
+    uniform 32-bit words drawn on the device from a seeded generator."""
+    from paper_2506_12761_amd.autotune import uniform_words
+    mode, M, l, lS, d = spec["mode"], spec["M"], spec["l"], spec["lS"], spec["d"]
+    q_shape = (d, l) if mode != "idm" else (l,)
+    loc_shape = {"intv": (M, d, 2, l), "cov": (M, d, l), "idm": (M, l)}[mode]
+    d_q = uniform_words(ctx, q_shape + (631,), seed)
+    d_loc = uniform_words(ctx, loc_shape + (631,), seed + 1)
+    d_pay = uniform_words(ctx, (M, lS, 631), seed + 2) if lS else None
+    d_R = ctx.empty(lS, 631) if lS else None
+    return d_q, d_loc, d_pay, d_R, ctx.empty(M, 631)
+
+
+def br_roofline(prof):
+    """Blind-rotation kernel rate against the derived integer peak, from the
+    library's per-launch HIP-event timing, and the key-switching share."""
+    br, ks = prof["br"], prof["ks"]
+    avg_ms = br["ms"] / br["launches"]
+    achieved = MODMUL_PER_BR * br["items"] / br["launches"] / (avg_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MODMUL / 1e12, "unit": "Tmodmul/s",
+            "frac": achieved / PEAK_MODMUL, "launches": br["launches"], "avg_launch_ms": avg_ms,
+            "ks_kernel_ms_share": ks["ms"] / max(1e-9, ks["ms"] + br["ms"]),
+            "ks_launches": ks["launches"], "ks_ms": ks["ms"]}
+
+
+def config4_query(ctx, ks, seed=0x5EED0004):
+    """One full identifier-match query (Alg. 3: equality of 32-bit
+    identifiers, Alg. 9 selection of 64 payload bits, pairwise XOR
+    aggregation) over 65,536 records, inputs resident on the device; timed
+    with HIP events on the library's stream, level by level."""
+    import torch
+
+    from paper_2506_12761_amd import vlp
+    spec = dict(CONFIG4)
+    bufs = device_inputs(ctx, spec, seed)
+    shape = vlp.make_shape(spec["mode"], spec["M"], spec["l"], spec["lS"], spec["d"])
+    t0 = time.perf_counter()
+    prog = vlp.vlp_program_create(ctx.ctx, ks, shape, *bufs)
+    build_s = time.perf_counter() - t0
+    counts = vlp.vlp_program_counts(ctx.ctx, prog)
+    log("config 4: %s, program built in %.1f s" % (counts, build_s))
+    vlp.vlp_profile_enable(ctx.ctx, True)
+    vlp.vlp_profile_read(ctx.ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.sync()
+    t0 = time.perf_counter()
+    e0.record(ctx.stream)
+    level = 0
+    while True:
+        rem = vlp.vlp_step(ctx.ctx, [prog])
+        level += 1
+        ctx.sync()
+        log("config 4: level %d of %d done, %.1f s" % (level, counts["levels"], time.perf_counter() - t0))
+        if not rem:
+            break
+    e1.record(ctx.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = vlp.vlp_profile_read(ctx.ctx)
+    vlp.vlp_profile_enable(ctx.ctx, False)
+    vlp.vlp_program_destroy(ctx.ctx, prog)
+    del bufs
+    torch.cuda.empty_cache()
+    return {"workload": "identifier match, 65536 records, 32-bit ids, 64-bit payload selection + pairwise XOR tree",
+            "programs": [spec], "value": counts["blind_rotations"] / (ms * 1e-3), "unit": "bootstraps/s",
+            "s_per_query": ms * 1e-3, "gates_per_s": counts["gates"] / (ms * 1e-3),
+            "blind_rotations": counts["blind_rotations"], "key_switches": counts["key_switches"],
+            "levels": counts["levels"], "program_build_s": build_s, "roofline": br_roofline(prof)}
 
 
 def mixed_programs(cells=4096, seed=0x5EED0003):
@@ -339,8 +415,8 @@ def main():
     ap.add_argument("--br-rotations-per-block", type=int, default=0,
                     help="blind rotations per workgroup (1, 2, 4; 8 with one wavefront per rotation)")
     ap.add_argument("--br-blocks", type=int, default=0, help="blind-rotation workgroups per CU the grid is sized for")
-    ap.add_argument("--ks-gates-per-block", type=int, default=0, choices=(0, 4, 8, 16),
-                    help="gates sharing one pass over the key-switching key (0: library default)")
+    ap.add_argument("--ks-gates-per-block", type=int, default=0, choices=(0, 128, 256, 512),
+                    help="most gates a key-switching workgroup takes (0: library default)")
     ap.add_argument("--br-waves-per-rotation", type=int, default=-1, choices=(-1, 0, 1, 2, 4),
                     help="wavefronts per blind rotation (0: automatic by launch size)")
     ap.add_argument("--serve", action="store_true", help="run the serving experiment instead")
@@ -352,6 +428,8 @@ def main():
     ap.add_argument("--min-records", type=int, default=256)
     ap.add_argument("--max-records", type=int, default=2048)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--no-config4", action="store_true",
+                    help="skip the 65,536-record identifier-match query reported beside the main line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device with a plain copy kernel (counter calibration)")
     args = ap.parse_args()
@@ -377,10 +455,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
         return
 
-    import numpy as np
     import torch
-
-    import synth
 
     from paper_2506_12761_amd import vlp
     assert torch.cuda.is_available(), "no HIP device"
@@ -390,10 +465,11 @@ def main():
         for p in specs:
             p["M"] = args.records
 
-    log("generating synthetic keys and ciphertexts ...")
-    bk, ksk = synth.uniform_keys(0x5EED0002)
+    from paper_2506_12761_amd.autotune import uniform_words
+    log("generating synthetic keys and ciphertexts on the device ...")
     ctx = vlp.Context(0)
-    ks = ctx.load_keys(bk, ksk)
+    ks = ctx.load_keys(uniform_words(ctx, (630, 6, 2, 1024), 0x5EED0002),
+                       uniform_words(ctx, (1024, 8, 4, 631), 0x5EED0012))
     if args.tuned:
         from paper_2506_12761_amd import autotune
         log("cached tuning applied: %s" % autotune.load_cached(ctx, args.workload))
@@ -408,17 +484,10 @@ def main():
               "br_blocks_per_cu": t.br_blocks_per_cu, "ks_gates_per_block": t.ks_gates_per_block}
     progs, keep = [], []
     for k, p in enumerate(specs):
-        mode, M, l, lS, d = p["mode"], p["M"], p["l"], p["lS"], p["d"]
-        q_shape = (d, l) if mode != "idm" else (l,)
-        loc_shape = {"intv": (M, d, 2, l), "cov": (M, d, l), "idm": (M, l)}[mode]
-        d_q = ctx.tensor(synth.uniform_ciphertexts(0x5EED0002, "query%d" % k, q_shape))
-        d_loc = ctx.tensor(synth.uniform_ciphertexts(0x5EED0002, "db_loc%d" % k, loc_shape))
-        d_pay = ctx.tensor(synth.uniform_ciphertexts(0x5EED0002, "db_pay%d" % k, (M, lS))) if lS else None
-        d_R = ctx.empty(lS, 631) if lS else None
-        d_v = ctx.empty(M, 631)
-        keep.append((d_q, d_loc, d_pay, d_R, d_v))
-        shape = vlp.make_shape(mode, M, l, lS, d, True, args.agg_k if lS else 0)
-        progs.append(vlp.vlp_program_create(ctx.ctx, ks, shape, d_q, d_loc, d_pay, d_R, d_v))
+        bufs = device_inputs(ctx, p, 0x5EED0100 + 16 * k)
+        keep.append(bufs)
+        shape = vlp.make_shape(p["mode"], p["M"], p["l"], p["lS"], p["d"], True, args.agg_k if p["lS"] else 0)
+        progs.append(vlp.vlp_program_create(ctx.ctx, ks, shape, *bufs))
     counts = [vlp.vlp_program_counts(ctx.ctx, pr) for pr in progs]
     br_step = sum(c["blind_rotations"] for c in counts)
     ks_step = sum(c["key_switches"] for c in counts)
@@ -472,8 +541,8 @@ def main():
 
     # Plain form: one AND gate per launch, launched back to back.
     P = args.plain_gates
-    a = ctx.tensor(synth.uniform_ciphertexts(7, "plain_a", (P,)))
-    b = ctx.tensor(synth.uniform_ciphertexts(7, "plain_b", (P,)))
+    a = uniform_words(ctx, (P, 631), 7)
+    b = uniform_words(ctx, (P, 631), 8)
     o = ctx.empty(P, 631)
     vlp.vlp_gate(ctx.ctx, ks, "AND", a[0:1], b[0:1], None, o[0:1], 1)
     ctx.sync()
@@ -487,23 +556,18 @@ def main():
     roofline = None
     if prof and prof["br"]["launches"]:
         br = prof["br"]
-        avg_ms = br["ms"] / br["launches"]
         # Algorithmic bytes per launch: the transformed key once (61,931,520 B), the two
         # input ciphertexts (2 x 2,524 B) and the extracted output (4,100 B) per rotation.
         alg_bytes = 61931520 + (2 * 2524 + 4100) * br["items"] / br["launches"]
-        per_launch = MODMUL_PER_BR * br["items"] / br["launches"]
-        achieved = per_launch / (avg_ms * 1e-3)
         traffic = None
         if (args.workload == "intv-1024" and TRAFFIC_MEASURED["kernel_sha"] == kernel_sha()
                 and TRAFFIC_MEASURED["launch"] == launch):
             traffic = TRAFFIC_MEASURED["bytes_per_launch"]
-        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_MODMUL / 1e12,
-                    "unit": "Tmodmul/s", "frac": achieved / PEAK_MODMUL, "traffic": traffic,
-                    "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": alg_bytes,
-                    "kernel": {0: "br2_kernel (br4_kernel for short rounds)", 1: "br_kernel", 2: "br2_kernel",
-                               4: "br4_kernel"}[launch["br_waves_per_rotation"]],
-                    "launches": br["launches"], "avg_launch_ms": avg_ms,
-                    "ks_kernel_ms_share": prof["ks"]["ms"] / max(1e-9, prof["ks"]["ms"] + br["ms"])}
+        roofline = br_roofline(prof)
+        achieved = roofline["achieved"] * 1e12
+        roofline.update({"traffic": traffic, "traffic_unit": "B per launch", "algorithmic_bytes_per_launch": alg_bytes,
+                         "kernel": {0: "br2_kernel (br4_kernel for short rounds)", 1: "br_kernel", 2: "br2_kernel",
+                                    4: "br4_kernel"}[launch["br_waves_per_rotation"]]})
         # Beside the derived peak: the measured rate of the transforms' own residue
         # butterflies (register-resident, every CU busy, the 6:2 forward:inverse mix of
         # a CMux), two of which make one modular multiplication.
@@ -512,6 +576,19 @@ def main():
         roofline["frac_of_peak_measured"] = achieved / (mp["mixed"] / RESIDUES_PER_MODMUL)
         log("measured residue-butterfly peak: %.3f T/s forward, %.3f T/s inverse, %.3f T/s mixed"
             % (mp["fwd"] / 1e12, mp["inv"] / 1e12, mp["mixed"] / 1e12))
+
+    config4 = None
+    if not args.no_config4 and args.workload != "idm-65536":
+        for pr in progs:
+            vlp.vlp_program_destroy(ctx.ctx, pr)
+        progs = []
+        del keep
+        torch.cuda.empty_cache()
+        config4 = config4_query(ctx, ks)
+        log("config 4: %.1f s per query, %.0f bootstraps/s, blind rotation %.1f%% of the derived peak, "
+            "key switching %.1f%% of kernel time" % (config4["s_per_query"], config4["value"],
+                                                     100 * config4["roofline"]["frac"],
+                                                     100 * config4["roofline"]["ks_kernel_ms_share"]))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -542,6 +619,7 @@ def main():
         "query_latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "config4": config4,
     }
     print(json.dumps(out), flush=True)
     for pr in progs:

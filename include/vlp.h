@@ -128,9 +128,9 @@ vlp_status vlp_mem_info(const vlp_ctx *ctx, size_t *used, size_t *budget);
  * key-switching key).  bk_dev: [630][6][2][1024], ksk_dev: [1024][8][4][631]
  * device arrays in the layouts above; they are read during the call's stream
  * work and may be freed after vlp_sync().  The keyset holds the bootstrapping
- * key transformed for the exact negacyclic products (61,931,520 B) and a
- * re-laid key-switching key with the digit-0 rows dropped and rows
- * padded to 640 words (62,914,560 B).  VLP_EBUDGET if it does not fit. */
+ * key transformed for the exact negacyclic products (61,931,520 B) and the
+ * key-switching key as signed byte planes for the 8-bit matrix cores
+ * (83,886,080 B).  VLP_EBUDGET if it does not fit. */
 vlp_status vlp_keyset_load(vlp_ctx *ctx, const uint32_t *bk_dev, const uint32_t *ksk_dev, vlp_keyset **out);
 
 /* Frees a keyset (VLP_EBUSY while programs made with it are alive). */
@@ -161,7 +161,7 @@ vlp_status vlp_gate(vlp_ctx *ctx, const vlp_keyset *ks, vlp_gate_op op, const ui
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same gates, bit for bit, with the intermediate ciphertexts and work items
  * in a fixed scratch array that the library holds on each device for the
- * life of the process (8,568,832 B), so the call makes no hipMalloc/hipFree.
+ * life of the process (10,665,984 B), so the call makes no hipMalloc/hipFree.
  * B <= 1024 gates per call (VLP_EINVAL above that).  Every call on one
  * device shares that device's array: calls that overlap in time on the same
  * device (two contexts or two streams) race and give wrong results; calls
@@ -249,8 +249,10 @@ vlp_status vlp_program_destroy(vlp_program *prog);
  * br_blocks_per_cu      : workgroups per compute unit a launch is sized for
  *                          (1..64); one launch covers br_blocks_per_cu x
  *                          br_rotations_per_block rotations per CU
- * ks_gates_per_block    : gates sharing one pass over the key-switching key (4, 8
- *                          (default), 16) */
+ * ks_gates_per_block    : most gates a key-switching workgroup takes, sharing
+ *                          its reads of the key (128, 256, 512 (default));
+ *                          each launch picks the tile (up to this) and the
+ *                          split of the coefficients over workgroups */
 typedef struct {
     uint32_t br_rotations_per_block;
     uint32_t br_blocks_per_cu;

@@ -22,9 +22,9 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.j
 
 # (wavefronts per rotation, rotations per workgroup, workgroups per CU, gates
 # per key-switching workgroup); 0 wavefronts per rotation = automatic by launch size
-SHAPES = ([(1, w, b, k) for w in (1, 2, 4, 8) for b in (1, 2, 4) for k in (4, 8) if w * b <= 8]
-          + [(r, q, b, k) for r in (0, 2) for (q, b) in ((1, 4), (2, 2), (4, 1)) for k in (4, 8, 16)]
-          + [(4, 1, b, k) for b in (1, 2) for k in (4, 8)])
+SHAPES = ([(1, w, b, 512) for w in (1, 2, 4, 8) for b in (1, 2, 4) if w * b <= 8]
+          + [(r, q, b, k) for r in (0, 2) for (q, b) in ((1, 4), (2, 2), (4, 1)) for k in (128, 256, 512)]
+          + [(4, 1, b, 512) for b in (1, 2)])
 
 
 def _apply(ctx, best: dict) -> None:

@@ -15,7 +15,6 @@ constexpr int KS_BASEBIT = 2;       // key-switching base 2^2
 constexpr int KS_T = 8;             // key-switching levels
 constexpr int CT_n = LWE_n + 1;     // words of an LWE_n ciphertext
 constexpr int CT_N = RING_N + 1;    // words of an LWE_N ciphertext
-constexpr int KS_ROW = 640;         // padded words per key-switching-key row (>= 631)
 constexpr uint32_t MU = 0x20000000u; // 1/8
 
 // Transformed bootstrapping key: [630][6 rows][2 components][1024] residue
@@ -24,8 +23,14 @@ constexpr uint32_t MU = 0x20000000u; // 1/8
 // by 1/1024 and kept in Montgomery form (times 2^32 mod P).
 constexpr size_t BK_ROW_WORDS = (size_t)2 * ELL * 2 * 2 * RING_N;  // one key row i: [6][2][2 primes][1024] words
 constexpr size_t BK_NTT_WORDS = (size_t)LWE_n * BK_ROW_WORDS;
-// Re-laid key-switching key: [1024][8][3 digits 1..3][640] words.
-constexpr size_t KSK_WORDS = (size_t)RING_N * KS_T * 3 * KS_ROW;       // u32 words
+// Key-switching key laid out for the 8-bit matrix cores, as byte planes:
+// [1024 coefficients i][20 tiles of 32 output words][4 byte planes p][64
+// lanes][4 words t].  Lane n + 32 h, word t holds, for output word
+// 32 * tile + n and level j = 4 h + t, byte p of the entries [i][j][v] for
+// v = 0..3 in bytes v = 0..3, each XOR 0x80 (a signed byte: value - 128); the
+// entry v = 0 and the words past 630 are zero.
+constexpr int KS_TILES = 20;                                        // 640 words / 32
+constexpr size_t KSK_WORDS = (size_t)RING_N * KS_TILES * 4 * 64 * 4;  // u32 words (83,886,080 B)
 
 // One blind rotation: input = (0, cst) + ca * a + cb * b + cm * (more[0] +
 // ... + more[n_more - 1]), output the sample-extracted LWE_N ciphertext of
@@ -54,12 +59,13 @@ struct KsItem {
 
 // Fixed device scratch of the allocation-free gate call (vlp_gate_noalloc):
 // the sample-extracted outputs of up to 2 blind rotations per gate, then the
-// blind-rotation and key-switching work items, for at most
+// blind-rotation and key-switching work items and the key-switching digits
+// (2 KiB per gate), for at most
 // NOALLOC_MAX_GATES gates per call.  One copy per device, in kernels.hip.
 constexpr size_t NOALLOC_MAX_GATES = 1024;
 constexpr size_t NOALLOC_EXT_BYTES = 2 * NOALLOC_MAX_GATES * CT_N * 4;   // multiple of 256
 constexpr size_t NOALLOC_BYTES = NOALLOC_EXT_BYTES + 2 * NOALLOC_MAX_GATES * sizeof(BrItem) +
-                                 NOALLOC_MAX_GATES * sizeof(KsItem);
+                                 NOALLOC_MAX_GATES * sizeof(KsItem) + NOALLOC_MAX_GATES * RING_N * 2;
 // Device address of the current device's copy of that scratch (the HIP error
 // of the lookup; call with the device current).
 int noalloc_scratch_address(void** p);
@@ -78,8 +84,14 @@ int launch_br2(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_
                void* stream);
 // Four wavefronts per rotation (prime x accumulator half), one rotation per workgroup.
 int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_t blocks, void* stream);
-int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block,
-                    uint32_t min_blocks, void* stream);
+// Key switching of count items on the matrix cores, in launches of at most
+// KS_CHUNK gates; dig: device scratch of ks_digit_bytes(count) bytes;
+// gates_per_block is the most gates a workgroup takes (128, 256 or 512), cus
+// the device's CUs.
+constexpr uint32_t KS_CHUNK = 16384;
+constexpr size_t ks_digit_bytes(size_t count) { return (count < KS_CHUNK ? count : KS_CHUNK) * (RING_N * 2); }
+int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t* dig,
+                    uint32_t gates_per_block, uint32_t cus, void* stream);
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,
                          uint32_t cst, uint32_t mu, uint32_t* out, const uint32_t* bk, void* stream);
 int launch_make_ks_items(KsItem* items, uint32_t count, const uint32_t* u1, const uint32_t* u2, uint32_t cst,

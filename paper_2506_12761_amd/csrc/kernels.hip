@@ -2,6 +2,7 @@
 // sample extraction, batched key switching, and small helpers.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <type_traits>
 
 #include "internal.h"
@@ -50,14 +51,21 @@ __global__ __launch_bounds__(64 * WAVES) void bk_transform_kernel(const uint32_t
   }
 }
 
-// ksk_out[i][j][v-1][w] = ksk_in[i][j][v][w] for v = 1..3, w < 631; pad words are 0.
+// The key-switching key [1024][8][4][631] in the byte-plane layout of
+// KSK_WORDS (internal.h), one output word per thread.
 __global__ void ksk_relayout_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out) {
-  const size_t total = KSK_WORDS;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-    const uint32_t w = (uint32_t)(idx % KS_ROW);
-    const size_t row = idx / KS_ROW;            // (i*8 + j)*3 + (v-1)
-    const size_t ij = row / 3, v = row % 3 + 1;
-    out[idx] = w < (uint32_t)CT_n ? in[(ij * 4 + v) * CT_n + w] : 0u;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < KSK_WORDS;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t t = idx & 3, lane = (idx >> 2) & 63, p = (idx >> 8) & 3;
+    const size_t rest = idx >> 10;
+    const uint32_t tile = (uint32_t)(rest % KS_TILES), i = (uint32_t)(rest / KS_TILES);
+    const uint32_t j = 4 * (lane >> 5) + t, w = 32 * tile + (lane & 31);
+    uint32_t word = 0x80u;  // v = 0: the zero entry
+    for (uint32_t v = 1; v < 4; ++v) {
+      const uint32_t k = w < (uint32_t)CT_n ? in[(((size_t)i * KS_T + j) * 4 + v) * CT_n + w] : 0u;
+      word |= (((k >> (8 * p)) & 0xFFu) ^ 0x80u) << (8 * v);
+    }
+    out[idx] = word;
   }
 }
 
@@ -561,89 +569,141 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 }
 
 // ---------------------------------------------------------------------------
-// Key switching: a block handles T gates that share each key row it reads,
-// over 1/SPLIT of the 1,024 input coefficients; each of the block's 320
-// threads owns two of the 640 padded output words.  With SPLIT > 1 the SPLIT
-// blocks of a gate group add their partial sums into outputs zeroed first
-// (32-bit atomic adds: the order of the additions does not change the result).
-// Key rows read per gate: 3 x 8 x 1,024 x 2.5 KB / T.
+// Key switching on the 8-bit matrix cores.
+//
+// The key switch of gate g subtracts, for every coefficient i < 1024 and
+// level j < 8, the key entry selected by the digit d_ij of a'_i + 2^15.  With
+// A[g][(i, j, v)] = [d_ij = v] (exactly one 1 per (i, j), the entry v = 0
+// being zero) that sum is the product A x K of the one-hot matrix and the key
+// K[(i, j, v)][w]; split K into byte planes K_p (so K = sum_p 2^(8p) K_p) and
+// each plane's product is an exact integer (at most 8,192 terms below 2^8),
+// computed by v_mfma_i32_32x32x32_i8 on signed bytes K_p - 128 (stored XOR
+// 0x80); every (i, j) contributes exactly one -128, so the word is
+// sum_p 2^(8p) C_p + 128 x (pairs) x 0x01010101 (mod 2^32).
+//
+// K-block of one MFMA = one coefficient i: lane n + 32 h supplies, in its 16
+// operand bytes t*4 + v, the levels j = 4 h + t and the digit values v (the
+// key lane of the same index supplies the same (j, v)); the gate rows of the
+// A operand are the lanes' n, the output words of the B operand the lanes' n.
+// A workgroup of 4 wavefronts covers 4 x RT x 32 gates and one tile of 32
+// output words (4 planes = 4 accumulators per 32 gates); blockIdx.z takes a
+// range of coefficients, whose partial results are added atomically into
+// outputs zeroed first when there is more than one range.
 // ---------------------------------------------------------------------------
-constexpr int KS_THREADS = 320;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
-template <int T, int SPLIT>
-__global__ __launch_bounds__(KS_THREADS) void ks_kernel(const KsItem* __restrict__ items, uint32_t count,
-                                                         const uint32_t* __restrict__ ksk) {
-  constexpr int NI = RING_N / SPLIT;
-  __shared__ uint32_t s_a[T][NI];
-  const uint32_t base = blockIdx.x * T;
-  const int i0 = blockIdx.y * NI;
-  const int nt = (int)min((uint32_t)T, count - base);
-  for (int idx = threadIdx.x; idx < T * NI; idx += KS_THREADS) {
-    const int g = idx / NI, i = i0 + idx % NI;
-    uint32_t a = 0;
-    if (g < nt) {
-      const KsItem& it = items[base + g];
-      a = it.u1[i] + (it.u2 ? it.u2[i] : 0u);
-    }
-    s_a[g][i - i0] = a + (1u << 15);  // rounding offset of the key-switching digits
-  }
-  const int w0 = threadIdx.x, w1 = threadIdx.x + KS_THREADS;
-  uint32_t acc[T][2];
+// Digit bytes of count gates (input a' = u1 + u2):
+// dig[(q * count + g) * 2 + h], byte c = bits [24 - 8h, 32 - 8h) of
+// a'_(4q+c) + 2^15, i.e. the digits of levels 4h .. 4h + 3 of coefficient
+// 4q + c, most significant first.  With zero_out the outputs are cleared
+// (split key switching adds into them).  One thread per (q, g), g fastest.
+__global__ void ks_prep_kernel(const KsItem* __restrict__ items, uint32_t count, uint2* __restrict__ dig,
+                               int zero_out) {
+  const size_t total = (size_t)count * (RING_N / 4);
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t g = (uint32_t)(t % count), q = (uint32_t)(t / count);
+    const KsItem& it = items[g];
+    const g_u32* u1 = (const g_u32*)it.u1 + 4 * q;
+    const g_u32* u2 = it.u2 ? (const g_u32*)it.u2 + 4 * q : nullptr;
+    uint32_t hi = 0, lo = 0;
 #pragma unroll
-  for (int g = 0; g < T; ++g) {
-    uint32_t body = 0;
-    if (blockIdx.y == 0 && g < nt && w1 == LWE_n) {  // the body word sits in the second half (320 <= 630 < 640)
-      const KsItem& it = items[base + g];
-      body = it.u1[RING_N] + (it.u2 ? it.u2[RING_N] : 0u) + it.cst;
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t a = u1[c] + (u2 ? u2[c] : 0u) + 0x8000u;
+      hi |= (a >> 24) << (8 * c);
+      lo |= ((a >> 16) & 0xFFu) << (8 * c);
     }
-    acc[g][0] = 0;
-    acc[g][1] = body;
-  }
-  __syncthreads();
-  for (int i = i0; i < i0 + NI; ++i) {
-    uint32_t a[T];
+    dig[t] = make_uint2(hi, lo);
+    if (zero_out && 4 * q < (uint32_t)CT_n)
 #pragma unroll
-    for (int g = 0; g < T; ++g) a[g] = s_a[g][i - i0];
-#pragma unroll 2
-    for (int j = 0; j < KS_T; ++j) {
-      const uint32_t* row = ksk + (size_t)((i * KS_T + j) * 3) * KS_ROW;
-      const uint32_t k10 = row[w0], k11 = row[w1];
-      const uint32_t k20 = row[KS_ROW + w0], k21 = row[KS_ROW + w1];
-      const uint32_t k30 = row[2 * KS_ROW + w0], k31 = row[2 * KS_ROW + w1];
-      const int sh = 30 - 2 * j;
-#pragma unroll
-      for (int g = 0; g < T; ++g) {
-        // Digit d = 2 b1 + b0 selects row d (none for 0).  The digit is the
-        // same for the whole workgroup: two scalar bit tests give the masks
-        // of three selects per word.
-        const bool b0 = (a[g] >> sh) & 1u, b1 = (a[g] >> (sh + 1)) & 1u;
-        const uint32_t s0 = b0 ? (b1 ? k30 : k10) : (b1 ? k20 : 0u);
-        const uint32_t s1 = b0 ? (b1 ? k31 : k11) : (b1 ? k21 : 0u);
-        acc[g][0] -= s0;
-        acc[g][1] -= s1;
-      }
-    }
-  }
-#pragma unroll
-  for (int g = 0; g < T; ++g) {
-    if (g < nt) {
-      uint32_t* out = items[base + g].out;
-      if (SPLIT == 1) {
-        if (w0 < CT_n) out[w0] = acc[g][0];
-        if (w1 < CT_n) out[w1] = acc[g][1];
-      } else {
-        if (w0 < CT_n) atomicAdd(out + w0, acc[g][0]);
-        if (w1 < CT_n) atomicAdd(out + w1, acc[g][1]);
-      }
-    }
+      for (int c = 0; c < 4; ++c)
+        if (4 * q + c < (uint32_t)CT_n) it.out[4 * q + c] = 0u;
   }
 }
 
-// Zeroes the outputs of count key-switching items (before split key switching).
-__global__ void ks_zero_kernel(const KsItem* __restrict__ items, uint32_t count) {
-  const size_t total = (size_t)count * CT_n;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x)
-    items[k / CT_n].out[k % CT_n] = 0u;
+template <int RT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4 / RT))) void ks_mfma_kernel(
+    const KsItem* __restrict__ items, uint32_t count,
+                                                      const uint32_t* __restrict__ dig,
+                                                      const uint4* __restrict__ ksk, uint32_t i_per_block) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t tile = blockIdx.x;
+  const uint32_t row0 = (blockIdx.y * 4 + wave) * (RT * 32);
+  const uint32_t i0 = blockIdx.z * i_per_block, i_end = i0 + i_per_block;
+  const int n = lane & 31, h = lane >> 5;
+  // Digit words of this lane's gate rows (rows past the last gate read the
+  // last gate's digits; their results are not stored).
+  const g_u32* dp[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) dp[rt] = (const g_u32*)dig + (size_t)min(row0 + rt * 32 + n, count - 1) * 2 + h;
+  const size_t dstep = (size_t)count * 2;  // words between coefficient groups
+  v16i acc[RT][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[rt][p] = v16i{};
+  // Key fragments of coefficient i: kb + i * KS_TILES * 256 (4 planes x 64 lanes).
+  const g_u32* kb = (const g_u32*)(ksk + (size_t)tile * 256 + lane);
+  auto load_b = [&](uint32_t i, v4i* b) {
+    const uint4* k = (const uint4*)(kb) + (size_t)i * KS_TILES * 256;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const uint4 v = k[p * 64];
+      b[p] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+    }
+  };
+  uint32_t dcur[RT], dnext[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) dcur[rt] = dp[rt][(size_t)(i0 / 4) * dstep];
+  v4i b0[4], b1[4];
+  load_b(i0, b0);
+  load_b(i0 + 1, b1);
+  for (uint32_t q = i0 / 4; q < i_end / 4; ++q) {
+    const uint32_t qn = min(q + 1, i_end / 4 - 1);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) dnext[rt] = dp[rt][(size_t)qn * dstep];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      v4i b[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        b[p] = b0[p];
+        b0[p] = b1[p];
+      }
+      load_b(min(4 * q + c + 2, i_end - 1), b1);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const uint32_t x = dcur[rt] >> (8 * c);
+        v4i a;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = (int)(1u << (((x >> (6 - 2 * t)) & 3u) << 3));
+#pragma unroll
+        for (int p = 0; p < 4; ++p) acc[rt][p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[p], acc[rt][p], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) dcur[rt] = dnext[rt];
+  }
+  const uint32_t corr = 128u * 8u * i_per_block * 0x01010101u;
+  const uint32_t w = tile * 32 + n;
+  if (w >= (uint32_t)CT_n) return;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t g = row0 + rt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      if (g >= count) continue;
+      const uint32_t sum = (uint32_t)acc[rt][0][r] + ((uint32_t)acc[rt][1][r] << 8) +
+                           ((uint32_t)acc[rt][2][r] << 16) + ((uint32_t)acc[rt][3][r] << 24) + corr;
+      const KsItem& it = items[g];
+      uint32_t val = 0u - sum;
+      if (w == (uint32_t)LWE_n && blockIdx.z == 0) val += it.u1[RING_N] + (it.u2 ? it.u2[RING_N] : 0u) + it.cst;
+      if (gridDim.z == 1)
+        it.out[w] = val;
+      else
+        atomicAdd(it.out + w, val);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -843,37 +903,48 @@ int launch_br4(const BrItem* items, uint32_t count, const uint4* tw_fwd, uint32_
   return (int)hipGetLastError();
 }
 
-int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t gates_per_block,
-                    uint32_t min_blocks, void* stream) {
-  if (count == 0) return 0;
-  // Launches too small to fill the device (fewer than min_blocks workgroups)
-  // split the coefficients 8 ways instead: 8x the workgroups, each walking an
-  // eighth of the key rows, which cuts the latency of a small launch.
-  const bool small = (count + gates_per_block - 1) / gates_per_block < min_blocks;
-  const uint32_t T = small ? 4 : gates_per_block;
-  const uint32_t groups = (count + T - 1) / T;
-  if (small || T != 4) {
-    const size_t words = (size_t)count * CT_n;
-    const uint32_t zb = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
-    hipLaunchKernelGGL(ks_zero_kernel, dim3(zb), dim3(256), 0, S(stream), items, count);
+int launch_ks_group(const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t* dig,
+                    uint32_t gates_per_block, uint32_t cus, void* stream) {
+  if (!(gates_per_block == 128 || gates_per_block == 256 || gates_per_block == 512)) return (int)hipErrorInvalidValue;
+  for (uint32_t first = 0; first < count; first += KS_CHUNK) {
+    const uint32_t cnt = std::min(KS_CHUNK, count - first);
+    // Gates per workgroup (gpb, at most gates_per_block; registers let a CU
+    // hold 512 / gpb such workgroups) and coefficient ranges per gate tile
+    // (sp): the pair that minimises the rounds of workgroups the device runs
+    // times the cycles of a round on one SIMD -- 512 matrix-core cycles per
+    // coefficient whatever the tile, plus the workgroups' epilogues (stores,
+    // or atomic adds when the ranges are split); larger tiles on ties (fewer
+    // key reads).
+    uint32_t gpb = gates_per_block, best = 1, rows = 1;
+    double best_cost = -1;
+    for (uint32_t g = gates_per_block; g >= 128; g /= 2)
+      for (uint32_t sp = 1; sp <= 32; sp *= 2) {
+        const uint32_t r = (cnt + g - 1) / g;
+        const double rounds = std::ceil((double)r * KS_TILES * sp / (cus * (512 / g)));
+        const double cost = rounds * ((double)(RING_N / sp) * 512.0 + (sp > 1 ? 8192.0 : 4096.0));
+        if (best_cost < 0 || cost < best_cost) {
+          gpb = g;
+          best = sp;
+          rows = r;
+          best_cost = cost;
+        }
+      }
+    const KsItem* it = items + first;
+    const size_t prep = (size_t)cnt * (RING_N / 4);
+    hipLaunchKernelGGL(ks_prep_kernel, dim3((uint32_t)std::min<size_t>((prep + 255) / 256, 8192)), dim3(256), 0,
+                       S(stream), it, cnt, reinterpret_cast<uint2*>(dig), best > 1 ? 1 : 0);
+    const dim3 grid(KS_TILES, rows, best);
+    const uint32_t ipb = RING_N / best;
+    const uint4* k = reinterpret_cast<const uint4*>(ksk);
+    switch (gpb) {
+      case 128: hipLaunchKernelGGL(ks_mfma_kernel<1>, grid, dim3(256), 0, S(stream), it, cnt, dig, k, ipb); break;
+      case 256: hipLaunchKernelGGL(ks_mfma_kernel<2>, grid, dim3(256), 0, S(stream), it, cnt, dig, k, ipb); break;
+      default: hipLaunchKernelGGL(ks_mfma_kernel<4>, grid, dim3(256), 0, S(stream), it, cnt, dig, k, ipb); break;
+    }
+    const int e = (int)hipGetLastError();
+    if (e != 0) return e;
   }
-  if (small) {
-    hipLaunchKernelGGL((ks_kernel<4, 8>), dim3(groups, 8), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
-    return (int)hipGetLastError();
-  }
-  switch (T) {
-    case 4:
-      hipLaunchKernelGGL((ks_kernel<4, 1>), dim3(groups), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
-      break;
-    case 8:
-      hipLaunchKernelGGL((ks_kernel<8, 2>), dim3(groups, 2), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
-      break;
-    case 16:
-      hipLaunchKernelGGL((ks_kernel<16, 4>), dim3(groups, 4), dim3(KS_THREADS), 0, S(stream), items, count, ksk);
-      break;
-    default: return (int)hipErrorInvalidValue;
-  }
-  return (int)hipGetLastError();
+  return 0;
 }
 
 int launch_make_br_items(BrItem* items, uint32_t count, const uint32_t* a, const uint32_t* b, int32_t ca, int32_t cb,

@@ -25,7 +25,7 @@ struct vlp_ctx {
   std::string err;
   uint4* tw_fwd = nullptr;  // device twiddle table
   int num_cus = 256;
-  vlp_tuning tune{4, 1, 8, 0};
+  vlp_tuning tune{4, 1, 512, 0};
   // Grow-only scratch for the elementwise calls.
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -65,6 +65,7 @@ struct vlp_program {
   uint32_t* gate_buf = nullptr;   // internal gate outputs [n_internal][631]
   uint32_t* ext_buf = nullptr;    // LWE_N slots [max BR per level][1025]
   const uint32_t** more_buf = nullptr;  // operand lists of k-input XOR items
+  uint32_t* dig_buf = nullptr;    // key-switching digits of one launch
   size_t bytes = 0;
   uint32_t max_br_level = 0;
   hipGraph_t graph = nullptr;
@@ -206,11 +207,11 @@ int timed_br(vlp_ctx* ctx, const BrItem* items, uint32_t count) {
   return 0;
 }
 
-int timed_ks(vlp_ctx* ctx, const KsItem* items, uint32_t count, const uint32_t* ksk) {
+int timed_ks(vlp_ctx* ctx, const KsItem* items, uint32_t count, const uint32_t* ksk, uint32_t* dig) {
   if (count == 0) return 0;
   const int m = mark_begin(ctx);
-  const int e = launch_ks_group(items, count, ksk, ctx->tune.ks_gates_per_block, (uint32_t)ctx->num_cus * 2,
-                                ctx->stream);
+  const int e =
+      launch_ks_group(items, count, ksk, dig, ctx->tune.ks_gates_per_block, (uint32_t)ctx->num_cus, ctx->stream);
   mark_end(ctx, m, 1, count);
   return e;
 }
@@ -394,7 +395,7 @@ extern "C" vlp_status vlp_set_tuning(vlp_ctx* ctx, const vlp_tuning* t) {
                              : (r == 4 ? rpb == 1 : (rpb == 1 || rpb == 2 || rpb == 4));
   if (!rpb_ok) return fail(ctx, VLP_EINVAL, "br_rotations_per_block %u not available with %u wavefronts per rotation", rpb, r);
   if (t->br_blocks_per_cu < 1 || t->br_blocks_per_cu > 64) return fail(ctx, VLP_EINVAL, "br_blocks_per_cu out of [1, 64]");
-  if (!(g == 4 || g == 8 || g == 16)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 4, 8 or 16");
+  if (!(g == 128 || g == 256 || g == 512)) return fail(ctx, VLP_EINVAL, "ks_gates_per_block must be 128, 256 or 512");
   ctx->tune = *t;
   return VLP_OK;
 }
@@ -474,11 +475,13 @@ extern "C" vlp_status vlp_keyswitch(vlp_ctx* ctx, const vlp_keyset* ks, const ui
   if (!ks || ks->ctx != ctx || !in_dev || !out_dev) return fail(ctx, VLP_EINVAL, "null or foreign argument");
   if (B > (1u << 26)) return fail(ctx, VLP_EINVAL, "B too large");
   if (ranges_overlap(in_dev, B * CT_N * 4, out_dev, B * CT_n * 4)) return fail(ctx, VLP_EINVAL, "in and out overlap");
-  vlp_status st = ensure_scratch(ctx, B * sizeof(KsItem));
+  const size_t item_bytes = (B * sizeof(KsItem) + 255) & ~(size_t)255;
+  vlp_status st = ensure_scratch(ctx, item_bytes + ks_digit_bytes(B));
   if (st != VLP_OK) return st;
   KsItem* items = (KsItem*)ctx->scratch;
+  uint32_t* dig = (uint32_t*)((char*)ctx->scratch + item_bytes);
   LAUNCHCHECK(ctx, launch_make_ks_items(items, (uint32_t)B, in_dev, nullptr, 0, out_dev, ks->ksk, ctx->stream));
-  LAUNCHCHECK(ctx, timed_ks(ctx, items, (uint32_t)B, ks->ksk));
+  LAUNCHCHECK(ctx, timed_ks(ctx, items, (uint32_t)B, ks->ksk, dig));
   return VLP_OK;
 }
 
@@ -502,10 +505,10 @@ vlp_status gate_args(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const u
 
 // Bytes of scratch a bootstrapped gate call over B gates lays out from `base`:
 // sample-extracted outputs (one or two per gate), then the blind-rotation and
-// key-switching items.
+// key-switching items, then the key-switching digits.
 constexpr size_t gate_scratch_bytes(vlp_gate_op op, size_t B) {
   return (((op == VLP_MUX ? 2 * B : B) * CT_N * 4 + 255) & ~(size_t)255) + (op == VLP_MUX ? 2 * B : B) * sizeof(BrItem) +
-         B * sizeof(KsItem);
+         B * sizeof(KsItem) + ks_digit_bytes(B);
 }
 static_assert(gate_scratch_bytes(VLP_MUX, NOALLOC_MAX_GATES) <= NOALLOC_BYTES, "fixed scratch too small");
 
@@ -518,6 +521,7 @@ vlp_status gate_run(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const ui
   uint32_t* ext = (uint32_t*)base;
   BrItem* bri = (BrItem*)((char*)base + ext_bytes);
   KsItem* ksi = (KsItem*)((char*)bri + units * sizeof(BrItem));
+  uint32_t* dig = (uint32_t*)((char*)ksi + B * sizeof(KsItem));
   int32_t ca, cb;
   uint32_t cst;
   gate_coeffs((uint8_t)op, &ca, &cb, &cst);
@@ -531,7 +535,7 @@ vlp_status gate_run(vlp_ctx* ctx, const vlp_keyset* ks, vlp_gate_op op, const ui
   if (e == 0)
     e = launch_make_ks_items(ksi, (uint32_t)B, ext, op == VLP_MUX ? ext + B * CT_N : nullptr, op == VLP_MUX ? MU : 0u,
                              out_dev, ks->ksk, ctx->stream);
-  if (e == 0) e = timed_ks(ctx, ksi, (uint32_t)B, ks->ksk);
+  if (e == 0) e = timed_ks(ctx, ksi, (uint32_t)B, ks->ksk, dig);
   ctx->prof = prof;
   if (e != 0) return fail(ctx, VLP_EHIP, "gate launch: %s", hipGetErrorString((hipError_t)e));
   return VLP_OK;
@@ -580,6 +584,7 @@ static void program_free(vlp_program* prog) {
   dev_free(ctx, prog->gate_buf, 0);
   dev_free(ctx, prog->ext_buf, 0);
   dev_free(ctx, prog->more_buf, 0);
+  dev_free(ctx, prog->dig_buf, 0);
   ctx->used -= prog->bytes;
   prog->ks->users--;
   ctx->live_programs--;
@@ -680,11 +685,12 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   // Gates by level.
   std::vector<std::vector<uint32_t>> by_level(nl.levels + 1);
   for (size_t g = 0; g < nl.gates.size(); ++g) by_level[nl.gates[g].level].push_back((uint32_t)g);
-  uint32_t max_br = 0;
+  uint32_t max_br = 0, max_ks = 0;
   for (uint32_t L = 1; L <= nl.levels; ++L) {
     uint32_t nbr = 0;
     for (uint32_t g : by_level[L]) nbr += nl.gates[g].op == VLP_MUX ? 2 : 1;
     max_br = std::max(max_br, nbr);
+    max_ks = std::max(max_ks, (uint32_t)by_level[L].size());
   }
   const uint64_t n_br = nl.blind_rotations(), n_ks = nl.key_switches();
   // Operand-list entries of the k-input XORs: the non-trivial operands past the first two.
@@ -698,7 +704,8 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   const size_t b_items = n_br * sizeof(BrItem), k_items = n_ks * sizeof(KsItem);
   const size_t b_gate = (size_t)n_internal * CT_n * 4, b_ext = (size_t)max_br * CT_N * 4;
   const size_t b_more = n_more * sizeof(const uint32_t*);
-  const size_t total = b_items + k_items + b_gate + b_ext + b_more;
+  const size_t b_dig = ks_digit_bytes(max_ks);
+  const size_t total = b_items + k_items + b_gate + b_ext + b_more + b_dig;
   if (ctx->used + total > ctx->budget)
     return fail(ctx, VLP_EBUDGET, "program needs %zu bytes; %zu of %zu in use", total, ctx->used, ctx->budget);
 
@@ -721,12 +728,14 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   if (e == hipSuccess && b_gate) e = hipMalloc((void**)&prog->gate_buf, b_gate);
   if (e == hipSuccess && b_ext) e = hipMalloc((void**)&prog->ext_buf, b_ext);
   if (e == hipSuccess && b_more) e = hipMalloc((void**)&prog->more_buf, b_more);
+  if (e == hipSuccess && b_dig) e = hipMalloc((void**)&prog->dig_buf, b_dig);
   if (e != hipSuccess) {
     (void)hipFree(prog->br_items);
     (void)hipFree(prog->ks_items);
     (void)hipFree(prog->gate_buf);
     (void)hipFree(prog->ext_buf);
     (void)hipFree(prog->more_buf);
+    (void)hipFree(prog->dig_buf);
     delete prog;
     return fail(ctx, VLP_EHIP, "program allocation: %s", hipGetErrorString(e));
   }
@@ -893,7 +902,7 @@ extern "C" vlp_status vlp_program_destroy(vlp_program* prog) {
 static vlp_status run_level(vlp_ctx* ctx, vlp_program* prog, uint32_t L) {
   const Level& lv = prog->levels[L];
   LAUNCHCHECK(ctx, timed_br(ctx, prog->br_items + lv.br_first, lv.br_count));
-  LAUNCHCHECK(ctx, timed_ks(ctx, prog->ks_items + lv.ks_first, lv.ks_count, prog->ks->ksk));
+  LAUNCHCHECK(ctx, timed_ks(ctx, prog->ks_items + lv.ks_first, lv.ks_count, prog->ks->ksk, prog->dig_buf));
   return VLP_OK;
 }
 
@@ -943,7 +952,8 @@ extern "C" vlp_status vlp_step(vlp_ctx* ctx, vlp_program* const* progs, size_t n
     for (size_t p = 0; p < n; ++p) {
       vlp_program* pr = progs[p];
       if (pr->next_level >= pr->levels.size()) continue;
-      LAUNCHCHECK(ctx, timed_ks(ctx, ksi + ks_groups[gi].first, (uint32_t)ks_groups[gi].second, pr->ks->ksk));
+      LAUNCHCHECK(ctx,
+                  timed_ks(ctx, ksi + ks_groups[gi].first, (uint32_t)ks_groups[gi].second, pr->ks->ksk, pr->dig_buf));
       gi++;
     }
   }

@@ -17,7 +17,7 @@ def test_multi_gpu_request_exits_with_message():
 
 
 def test_bad_key_switching_group_size_is_rejected():
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--ks-gates-per-block", "5"],
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--ks-gates-per-block", "8"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "invalid choice" in r.stderr
     assert r.stdout == ""
@@ -37,4 +37,4 @@ def test_roofline_constants():
     assert bench.MODMUL_PER_BR == 630 * (butterflies + products) == 33_546_240
     assert abs(bench.PEAK_MODMUL - 256 * 64 * 2.4e9 / 10) < 1.0
     assert bench.TRAFFIC_MEASURED["launch"] == {"br_waves_per_rotation": 0, "br_rotations_per_block": 4,
-                                                "br_blocks_per_cu": 1, "ks_gates_per_block": 8}
+                                                "br_blocks_per_cu": 1, "ks_gates_per_block": 512}

@@ -76,7 +76,7 @@ def test_keyset_of_another_context_is_rejected(gpu, oracle_keys):
 
 def test_budget_too_small_for_a_keyset(oracle_keys):
     from paper_2506_12761_amd import vlp
-    small = vlp.Context(0, hbm_budget=64 << 20)  # below the 124.8 MB a keyset needs
+    small = vlp.Context(0, hbm_budget=64 << 20)  # below the 145.8 MB a keyset needs
     try:
         used0, budget = vlp.vlp_mem_info(small.ctx)
         assert budget == 64 << 20
@@ -88,7 +88,8 @@ def test_budget_too_small_for_a_keyset(oracle_keys):
         small.close()
 
 
-@pytest.mark.parametrize("bad", [(1, 1, 4, 3), (8, 1, 4, 2), (2, 1, 4, 4), (4, 0, 4, 0), (4, 65, 4, 0), (4, 1, 5, 0)])
+@pytest.mark.parametrize("bad", [(1, 1, 512, 3), (8, 1, 512, 2), (2, 1, 512, 4), (4, 0, 512, 0), (4, 65, 512, 0),
+                                 (4, 1, 8, 0), (4, 1, 64, 0), (4, 1, 1024, 0)])
 def test_tuning_validation(gpu, bad):
     vlp, ctx, ks = gpu
     old = vlp.vlp_get_tuning(ctx.ctx)
@@ -165,7 +166,7 @@ def test_graph_follows_a_tuning_change(gpu, oracle_keys):
     v_want, R_want = W.oracle_outputs(oracle_keys, P, enc)
     old = vlp.vlp_get_tuning(ctx.ctx)
     try:
-        for tune in (None, (1, 2, 4, 4), (2, 1, 16, 2)):
+        for tune in (None, (1, 2, 128, 4), (2, 1, 256, 2)):
             if tune:
                 vlp.vlp_set_tuning(ctx.ctx, *tune)
             for _ in range(2):

@@ -48,14 +48,15 @@ def test_bootstrap_parity(gpu, oracle_keys):
             assert np.array_equal(got[b], want[b]), (mu, b)
 
 
-@pytest.mark.parametrize("gates_per_block,B", [(4, 21), (4, 8197), (8, 8197), (16, 8197)])
+@pytest.mark.parametrize("gates_per_block,B", [(128, 21), (512, 21), (128, 8197), (256, 8197), (512, 8197),
+                                               (512, 16384 + 8197), (512, 40000)])
 def test_keyswitch_parity(gpu, oracle_keys, gates_per_block, B):
-    """Every key-switching workgroup shape equals the oracle: launches too small
-    to fill the device (21 gates) split the coefficients 8 ways, large ones use
-    4, 8 or 16 gates per workgroup (8 and 16 split the coefficients over 2 and
-    4 workgroups); split partial sums are added atomically into outputs that
-    start dirty, so the zeroing is exercised; the last group is partial.  The
-    large launches are checked on 48 sampled gates."""
+    """Every key-switching tile shape on the matrix cores equals the oracle:
+    at most 128, 256 or 512 gates per workgroup, with the coefficients split
+    over up to 32 workgroups whose partial sums are added atomically into
+    outputs that start dirty (small launches), or not split; launches above
+    16,384 gates run as several launches sharing one digit buffer; the last
+    gate tile is partial.  Large launches are checked on 48 sampled gates."""
     vlp, ctx, ks = gpu
     ins = _rand_words(3 + B, (B, O.N + 1))
     ins[0] = 0
