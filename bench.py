@@ -329,6 +329,64 @@ def server_enc_bench(args):
     ctx.close()
 
 
+# Key switching on the matrix cores: per gate, a product of the one-hot digit
+# matrix (1,024 coefficients x 8 levels x 4 digit values = 32,768 columns)
+# with the key's 4 byte planes of 640 (631 padded) words, 2 ops per
+# multiply-add; dense int8 peak of MI355X 5.0 POP/s.  The method's own work is
+# at most 8,192 row subtractions of 631 words (5,169,152 adds; 3/4 of that on
+# average for uniform digits).
+KS_MFMA_OPS = 2 * 1024 * 8 * 4 * 640 * 4  # 167,772,160
+PEAK_INT8_OPS = 5.0e15
+KS_ADDS_MAX = 1024 * 8 * 631
+
+
+def keyswitch_bench(args):
+    """vlp_keyswitch over `--ks-gates` uniform LWE_N ciphertexts (one launch
+    of up to 16,384 gates per chunk), timed with HIP events on the library's
+    stream; rate against the int8 matrix-core peak."""
+    import torch
+
+    from paper_2506_12761_amd import vlp
+    from paper_2506_12761_amd.autotune import uniform_words
+    ctx = vlp.Context(0)
+    ks = ctx.load_keys(uniform_words(ctx, (630, 6, 2, 1024), 21), uniform_words(ctx, (1024, 8, 4, 631), 22))
+    if args.ks_gates_per_block:
+        t = vlp.vlp_get_tuning(ctx.ctx)
+        vlp.vlp_set_tuning(ctx.ctx, t.br_rotations_per_block, t.br_blocks_per_cu, args.ks_gates_per_block,
+                           t.br_waves_per_rotation)
+    B = args.ks_gates
+    d_in = uniform_words(ctx, (B, 1025), 23)
+    d_out = ctx.empty(B, 631)
+    for _ in range(max(1, args.warmup)):
+        vlp.vlp_keyswitch(ctx.ctx, ks, d_in, d_out, B)
+    ctx.sync()
+    vlp.vlp_profile_enable(ctx.ctx, True)
+    vlp.vlp_profile_read(ctx.ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    for _ in range(args.steps):
+        vlp.vlp_keyswitch(ctx.ctx, ks, d_in, d_out, B)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = vlp.vlp_profile_read(ctx.ctx)
+    rate = B / (ms * 1e-3)
+    ops = KS_MFMA_OPS * rate
+    t = vlp.vlp_get_tuning(ctx.ctx)
+    print(json.dumps({
+        "metric": "key switches/s at 1 GPU (LWE_1024 -> LWE_630, base 2^2, 8 levels)", "value": rate,
+        "unit": "key switches/s", "higher_is_better": True, "steps": args.steps, "warmup": args.warmup,
+        "dtype": "u32 (int8 matrix-core planes)", "data": "synthetic (seeded uniform key and ciphertexts)",
+        "config": {"workload": "%d key switches per call" % B, "ks_gates_per_block": t.ks_gates_per_block},
+        "ms_per_call": ms, "timed_calls_ms_per_call": prof["ks"]["ms"] / max(1, args.steps),
+        "roofline": {"bound": "mfma", "achieved": ops / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s (int8)",
+                     "frac": ops / PEAK_INT8_OPS, "traffic": None, "mfma_ops_per_key_switch": KS_MFMA_OPS},
+        "algorithmic": {"adds_per_s_max": KS_ADDS_MAX * rate, "adds_per_s_mean": 0.75 * KS_ADDS_MAX * rate,
+                        "key_bytes_per_call": 83886080 * -(-B // 16384)},
+    }), flush=True)
+    ctx.close()
+
+
 def serve_bench(args):
     """Poisson stream of PIR queries, modes uniform over {IntV 16-bit, CoV 20-bit,
     IdM 32-bit}, records log-uniform in [min, max], 64 payload bits, one of
@@ -428,6 +486,8 @@ def main():
     ap.add_argument("--min-records", type=int, default=256)
     ap.add_argument("--max-records", type=int, default=2048)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--keyswitch", action="store_true", help="time key switching alone instead")
+    ap.add_argument("--ks-gates", type=int, default=16384, help="key switches per call with --keyswitch")
     ap.add_argument("--no-config4", action="store_true",
                     help="skip the 65,536-record identifier-match query reported beside the main line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -444,6 +504,8 @@ def main():
         return table3_bench(args)
     if args.server_enc:
         return server_enc_bench(args)
+    if args.keyswitch:
+        return keyswitch_bench(args)
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
