@@ -387,70 +387,107 @@ def keyswitch_bench(args):
     ctx.close()
 
 
+class SkipIdleClock:
+    """Wall clock that skips the device's idle gaps: when no request is active
+    the server's wait for the next arrival advances this clock instead of
+    sleeping.  Nothing runs during such a gap, so no latency changes."""
+
+    def __init__(self):
+        self.offset = 0.0
+
+    def __call__(self):
+        return time.perf_counter() + self.offset
+
+    def sleep(self, dt):
+        self.offset += max(0.0, dt)
+
+
 def serve_bench(args):
-    """Poisson stream of PIR queries, modes uniform over {IntV 16-bit, CoV 20-bit,
-    IdM 32-bit}, records log-uniform in [min, max], 64 payload bits, one of
-    `clients` key sets each; reports latency percentiles (arrival to the
-    result R copied to the host) and queries/s."""
+    """Poisson stream of PIR queries (config 5): modes uniform over {IntV
+    16-bit, CoV 20-bit, IdM 32-bit}, records log-uniform in [min, max], 64
+    payload bits, full Alg. 3 with the pairwise XOR aggregation, one client
+    (own seeded keys) per request.  Keys and the request's encrypted database
+    are drawn on the device when the request is admitted (they count against
+    the HBM budget while it runs); latency runs from arrival to the result R
+    copied to the host.  Arrival rate = load x the calibrated saturated rate
+    of the stream's mean query."""
     import numpy as np
     import torch
 
     import synth
-
     from paper_2506_12761_amd import vlp
+    from paper_2506_12761_amd.autotune import uniform_words
     from paper_2506_12761_amd.serve import GpuExecutor, Request, poisson_arrivals, serve
     ctx = vlp.Context(0)
-    keysets = {}
-    for c in range(args.clients):
-        bk, ksk = synth.uniform_keys(0x5EED0005 + c)
-        keysets[c] = ctx.load_keys(bk, ksk)
     g = synth.stream(0x5EED0005, "serve")
     kinds = [("intv", 16, 2), ("cov", 20, 2), ("idm", 32, 1)]
     reqs = []
     for rid in range(args.requests):
         mode, l, d = kinds[int(g.integers(0, 3))]
         M = int(2 ** g.uniform(np.log2(args.min_records), np.log2(args.max_records)))
-        reqs.append(Request(rid, int(g.integers(0, args.clients)), mode, M, l, 64, d, arrival=0.0))
-    # Saturated rate estimate: blind rotations per query against a calibration run.
+        reqs.append(Request(rid, rid, mode, M, l, 64, d, arrival=0.0))
+
     def plan_br(r):
         return vlp.vlp_plan_counts(vlp.make_shape(r.mode, r.M, r.l_I, r.l_S, r.d))["blind_rotations"]
-    cal = Request(-1, 0, "intv", 256, 16, 0, 2, arrival=0.0)
-    q = ctx.tensor(synth.uniform_ciphertexts(1, "cq", (2, 16)))
-    loc = ctx.tensor(synth.uniform_ciphertexts(1, "cl", (256, 2, 2, 16)))
-    v = ctx.empty(256, 631)
-    sh = vlp.make_shape("intv", 256, 16, 0, 2)
-    vlp.vlp_evaluate(ctx.ctx, keysets[0], sh, q, loc, None, None, v)
-    ctx.sync()
-    t0 = time.perf_counter()
-    vlp.vlp_evaluate(ctx.ctx, keysets[0], sh, q, loc, None, None, v)
-    ctx.sync()
-    br_rate = plan_br(cal) / (time.perf_counter() - t0)
-    mean_br = sum(plan_br(r) for r in reqs) / len(reqs)
-    rate = args.load * br_rate / mean_br
-    arrivals = poisson_arrivals(rate, len(reqs), g)
-    for r, t in zip(reqs, arrivals):
-        r.arrival = t
+
+    def keys_of(client):
+        return (uniform_words(ctx, (630, 6, 2, 1024), 0x5EED0500 + 2 * client),
+                uniform_words(ctx, (1024, 8, 4, 631), 0x5EED0501 + 2 * client))
+
+    def inputs_of(r):
         shp = (r.d, r.l_I) if r.mode != "idm" else (r.l_I,)
         lshape = {"intv": (r.M, r.d, 2, r.l_I), "cov": (r.M, r.d, r.l_I), "idm": (r.M, r.l_I)}[r.mode]
-        r.payload = {"query": ctx.tensor(synth.uniform_ciphertexts(r.rid, "q", shp)),
-                     "db_loc": ctx.tensor(synth.uniform_ciphertexts(r.rid, "l", lshape)),
-                     "db_pay": ctx.tensor(synth.uniform_ciphertexts(r.rid, "p", (r.M, 64))),
-                     "R": ctx.empty(64, 631), "v": ctx.empty(r.M, 631)}
-    log("serving %d requests, rate %.4f/s (load %.2f of %.0f bootstraps/s)" % (len(reqs), rate, args.load, br_rate))
-    torch.cuda.synchronize()
-    st = serve(reqs, GpuExecutor(ctx, keysets), log=log)
+        return {"query": uniform_words(ctx, shp + (631,), 0x5EED1000 + 4 * r.rid),
+                "db_loc": uniform_words(ctx, lshape + (631,), 0x5EED1001 + 4 * r.rid),
+                "db_pay": uniform_words(ctx, (r.M, r.l_S, 631), 0x5EED1002 + 4 * r.rid),
+                "R": ctx.empty(r.l_S, 631), "v": ctx.empty(r.M, 631)}
+
+    # Saturated rate: blind rotations per second of one merged 1,024-record query.
+    cal = device_inputs(ctx, dict(mode="intv", M=1024, l=16, lS=0, d=2), 0x5EED0600)
+    bk, ksk = keys_of(10**6)
+    ks = ctx.load_keys(bk, ksk)
+    del bk, ksk
+    sh = vlp.make_shape("intv", 1024, 16, 0, 2)
+    vlp.vlp_evaluate(ctx.ctx, ks, sh, *cal)
+    ctx.sync()
+    t0 = time.perf_counter()
+    vlp.vlp_evaluate(ctx.ctx, ks, sh, *cal)
+    ctx.sync()
+    br_rate = vlp.vlp_plan_counts(sh)["blind_rotations"] / (time.perf_counter() - t0)
+    ctx.drop_keys(ks)
+    del cal
+    torch.cuda.empty_cache()
+    mean_br = sum(plan_br(r) for r in reqs) / len(reqs)
+    rate = args.arrival_rate or args.load * br_rate / mean_br
+    for r, t in zip(reqs, poisson_arrivals(rate, len(reqs), g)):
+        r.arrival = t
+    budget = int(args.hbm_budget_gb * 2**30)
+    log("serving %d requests, rate %.5f/s (load %.2f of %.0f bootstraps/s, mean query %.0f bootstraps), "
+        "policy %s, step cap %s, budget %.0f GiB" % (len(reqs), rate, args.load, br_rate, mean_br, args.policy,
+                                                      args.step_cap, args.hbm_budget_gb))
+    ex = GpuExecutor(ctx, key_factory=keys_of, input_factory=inputs_of, budget=budget)
+    clk = SkipIdleClock()
+    st = serve(reqs, ex, clock=clk, sleep=clk.sleep, log=log, policy=args.policy,
+               step_cap=args.step_cap or None)
     total_br = sum(plan_br(r) for r in st["requests"])
+    busy_s = st["wall_s"]
     out = {
         "metric": "PIR query latency under Poisson load (continuous batching), 1 GPU",
         "value": st["p50_ms"], "unit": "ms (p50)", "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "max_ms": max(r.latency for r in st["requests"]) * 1e3,
         "higher_is_better": False, "queries_per_s": st["queries_per_s"],
-        "bootstraps_per_s_during_serving": total_br / st["wall_s"], "n_gpus": 1,
+        "bootstraps_per_s_during_serving": total_br / busy_s, "n_gpus": 1,
         "queries": st["queries"], "steps": st["steps"], "max_active": st["max_active"],
         "budget_rejections": st["budget_rejections"], "arrival_rate_per_s": rate, "load": args.load,
-        "calibrated_bootstraps_per_s": br_rate, "dtype": "u32", "data": "synthetic (seeded uniform keys and ciphertexts)",
+        "calibrated_bootstraps_per_s": br_rate, "mean_query_bootstraps": mean_br,
+        "policy": args.policy, "step_cap": args.step_cap or None, "hbm_budget_bytes": budget,
+        "clock": "idle gaps between arrivals skipped (device idle; latencies unchanged)",
+        "dtype": "u32", "data": "synthetic (seeded uniform keys and ciphertexts, drawn on the device at admission)",
         "config": {"workload": "serving: modes uniform over IntV-16/CoV-20/IdM-32, records log-uniform "
-                               "%d..%d, 64 payload bits, %d clients" % (args.min_records, args.max_records, args.clients),
-                   "per_request": [(r.mode, r.M, round(r.latency * 1e3, 1)) for r in st["requests"]]},
+                               "%d..%d, 64 payload bits, one client per request" % (args.min_records,
+                                                                                     args.max_records),
+                   "per_request": [(r.mode, r.M, plan_br(r), round(r.arrival, 2), round(r.latency * 1e3, 1))
+                                   for r in st["requests"]]},
     }
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -481,11 +518,15 @@ def main():
     ap.add_argument("--table3", action="store_true", help="replay the paper's dataset shapes instead")
     ap.add_argument("--server-enc", action="store_true", help="time ServerEnc of a 65,536-record database instead")
     ap.add_argument("--progress", action="store_true", help="wait for and report every circuit level")
-    ap.add_argument("--requests", type=int, default=12)
-    ap.add_argument("--clients", type=int, default=3)
+    ap.add_argument("--requests", type=int, default=50)
     ap.add_argument("--min-records", type=int, default=256)
-    ap.add_argument("--max-records", type=int, default=2048)
+    ap.add_argument("--max-records", type=int, default=16384)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--arrival-rate", type=float, default=0.0, help="queries/s (overrides --load)")
+    ap.add_argument("--policy", default="srpt", choices=("all", "srpt"),
+                    help="which admitted queries a step advances (serve.py)")
+    ap.add_argument("--step-cap", type=int, default=65536, help="most blind rotations per step under srpt")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="device memory the server may hold")
     ap.add_argument("--keyswitch", action="store_true", help="time key switching alone instead")
     ap.add_argument("--ks-gates", type=int, default=16384, help="key switches per call with --keyswitch")
     ap.add_argument("--no-config4", action="store_true",

@@ -204,8 +204,9 @@ vlp_status vlp_server_encrypt(vlp_ctx *ctx, const vlp_shape *shape, const uint32
 
 /* ---- Programs: an evaluation bound to its buffers, advanced level by level.
  * vlp_program_create builds the gate schedule of vlp_evaluate's arguments
- * and reserves its intermediate storage (VLP_EBUDGET if the budget cannot
- * hold it).  vlp_step advances every unfinished program in progs[] by one
+ * and reserves its intermediate storage and its share of the context's
+ * merged-step scratch (VLP_EBUDGET if the budget, or the device, cannot hold
+ * it), so that vlp_step itself allocates nothing.  vlp_step advances every unfinished program in progs[] by one
  * circuit level in one merged batch of kernel launches, so gates of several
  * programs, keysets and modes share the same launches; *remaining receives
  * the number of programs in progs[] that still have levels to run; a program
@@ -226,6 +227,17 @@ vlp_status vlp_program_run(vlp_ctx *ctx, vlp_program *prog, int use_graph);
 /* The same counts for a shape, computed on the host without a device. */
 vlp_status vlp_plan_counts(const vlp_shape *shape, uint64_t *gates, uint64_t *blind_rotations, uint64_t *key_switches,
                            uint32_t *levels);
+/* Device bytes vlp_program_create would reserve against the budget for a
+ * shape (with or without a v_out buffer), computed on the host: work items,
+ * intermediate ciphertexts, key-switching digits and the program's share of
+ * the merged-step scratch that vlp_step uses.  A server can admit a request
+ * only when these bytes (plus its input buffers) fit.  VLP_EINVAL for a bad
+ * shape or a NULL argument. */
+vlp_status vlp_plan_bytes(const vlp_shape *shape, int with_v_out, size_t *bytes);
+/* Blind rotations and key switches of one level (0-based) of a program;
+ * VLP_EINVAL past the last level. */
+vlp_status vlp_program_level_counts(const vlp_program *prog, uint32_t level, uint64_t *blind_rotations,
+                                   uint64_t *key_switches);
 vlp_status vlp_program_counts(const vlp_program *prog, uint64_t *gates, uint64_t *blind_rotations,
                               uint64_t *key_switches, uint32_t *levels);
 vlp_status vlp_program_destroy(vlp_program *prog);

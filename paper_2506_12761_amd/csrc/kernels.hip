@@ -363,6 +363,11 @@ __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rot_i = wave >> 1, pr = wave & 1, t = threadIdx.x & 127;  // t: thread within the rotation's pair
+  // Wavefront w runs on SIMD w mod 4, so each SIMD holds rotation r and
+  // rotation r + 2 of the same prime, which reach their LDS waits together.
+  // Raising the first one's issue priority lets it run ahead until it waits
+  // while the other fills the gaps (12.21 -> 12.12 ms per launch).
+  if (ROT == 4 && rot_i < 2) __builtin_amdgcn_s_setprio(1);
   const uint2* gtw2 = reinterpret_cast<const uint2*>(tw_fwd);
   uint32_t* acc = s_acc[rot_i][0];
   uint16_t* abar = s_abar[rot_i];

@@ -31,6 +31,10 @@ struct vlp_ctx {
   size_t scratch_bytes = 0;
   // This device's fixed scratch for vlp_gate_noalloc (device address).
   void* noalloc = nullptr;
+  // Bytes of merged work items that vlp_step may need: the sum over live
+  // programs of their largest level's items; the scratch is kept at least
+  // this large from program creation on, so vlp_step never allocates.
+  size_t step_reserve = 0;
   int live_keysets = 0, live_programs = 0;
   std::list<vlp_program*> eval_cache;  // programs made by vlp_evaluate, most recent first
   // Kernel timing (vlp_profile_enable).
@@ -67,6 +71,7 @@ struct vlp_program {
   const uint32_t** more_buf = nullptr;  // operand lists of k-input XOR items
   uint32_t* dig_buf = nullptr;    // key-switching digits of one launch
   size_t bytes = 0;
+  size_t step_bytes = 0;  // its share of the context's step reserve
   uint32_t max_br_level = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -111,7 +116,9 @@ vlp_status dev_alloc(vlp_ctx* ctx, void** p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
-    return fail(ctx, VLP_EHIP, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    (void)hipGetLastError();
+    return fail(ctx, e == hipErrorOutOfMemory ? VLP_EBUDGET : VLP_EHIP, "hipMalloc(%zu): %s", bytes,
+                hipGetErrorString(e));
   }
   ctx->used += bytes;
   return VLP_OK;
@@ -586,6 +593,7 @@ static void program_free(vlp_program* prog) {
   dev_free(ctx, prog->more_buf, 0);
   dev_free(ctx, prog->dig_buf, 0);
   ctx->used -= prog->bytes;
+  ctx->step_reserve -= prog->step_bytes;
   prog->ks->users--;
   ctx->live_programs--;
   delete prog;
@@ -628,6 +636,72 @@ extern "C" vlp_status vlp_server_encrypt(vlp_ctx* ctx, const vlp_shape* shape, c
   return VLP_OK;
 }
 
+// Device memory of a program: work items, internal gate outputs, extraction
+// slots of its widest level, k-input XOR operand lists, key-switching digits,
+// and its share of the merged-step scratch.
+struct ProgramSizes {
+  std::vector<int32_t> slot;        // gate -> user output slot (v_out[i] = i, R[j] = M + j) or -1
+  std::vector<uint32_t> internal;   // gate -> internal buffer index (if slot < 0)
+  uint32_t n_internal = 0, max_br = 0, max_ks = 0;
+  uint64_t n_br = 0, n_ks = 0;
+  size_t n_more = 0;
+  size_t b_items = 0, k_items = 0, b_gate = 0, b_ext = 0, b_more = 0, b_dig = 0, total = 0, step = 0;
+};
+
+static const char* program_sizes(const Netlist& nl, bool with_v_out, ProgramSizes& z) {
+  const size_t M = nl.M, lS = nl.l_S;
+  z.slot.assign(nl.gates.size(), -1);
+  if (with_v_out)
+    for (size_t i = 0; i < M; ++i)
+      if (nl.v_of_record[i].src == Src::Gate) z.slot[nl.v_of_record[i].index] = (int32_t)i;
+  for (size_t j = 0; j < lS; ++j) {
+    const Operand& r = nl.result[j];
+    if (r.src != Src::Gate || z.slot[r.index] >= 0) return "a result bit is not a distinct gate";
+    z.slot[r.index] = (int32_t)(M + j);
+  }
+  z.internal.assign(nl.gates.size(), 0);
+  for (size_t g = 0; g < nl.gates.size(); ++g)
+    if (z.slot[g] < 0) z.internal[g] = z.n_internal++;
+  std::vector<uint32_t> nbr(nl.levels + 1, 0), nks(nl.levels + 1, 0);
+  for (const Gate& G : nl.gates) {
+    nbr[G.level] += G.op == VLP_MUX ? 2 : 1;
+    nks[G.level] += 1;
+  }
+  for (uint32_t L = 1; L <= nl.levels; ++L) {
+    z.max_br = std::max(z.max_br, nbr[L]);
+    z.max_ks = std::max(z.max_ks, nks[L]);
+  }
+  z.n_br = nl.blind_rotations();
+  z.n_ks = nl.key_switches();
+  // Operand-list entries of the k-input XORs: the non-trivial operands past the first two.
+  for (const Gate& G : nl.gates) {
+    if (G.op != OP_XORK) continue;
+    size_t live = (G.a.is_const() ? 0 : 1) + (G.b.is_const() ? 0 : 1);
+    for (uint32_t t = 0; t < G.xk_count; ++t) live += nl.xk_ops[G.xk_first + t].is_const() ? 0 : 1;
+    z.n_more += live > 2 ? live - 2 : 0;
+  }
+  z.b_items = z.n_br * sizeof(BrItem);
+  z.k_items = z.n_ks * sizeof(KsItem);
+  z.b_gate = (size_t)z.n_internal * CT_n * 4;
+  z.b_ext = (size_t)z.max_br * CT_N * 4;
+  z.b_more = z.n_more * sizeof(const uint32_t*);
+  z.b_dig = ks_digit_bytes(z.max_ks);
+  z.total = z.b_items + z.k_items + z.b_gate + z.b_ext + z.b_more + z.b_dig;
+  z.step = (((size_t)z.max_br * sizeof(BrItem) + 255) & ~(size_t)255) + (size_t)z.max_ks * sizeof(KsItem) + 256;
+  return nullptr;
+}
+
+extern "C" vlp_status vlp_plan_bytes(const vlp_shape* shape, int with_v_out, size_t* bytes) {
+  if (!shape || !bytes) return VLP_EINVAL;
+  Netlist nl;
+  const char* why = "";
+  if (!build_netlist(*shape, nl, &why)) return VLP_EINVAL;
+  ProgramSizes z;
+  if (program_sizes(nl, with_v_out != 0, z)) return VLP_EINVAL;
+  *bytes = z.total + z.step;
+  return VLP_OK;
+}
+
 extern "C" vlp_status vlp_plan_counts(const vlp_shape* shape, uint64_t* gates, uint64_t* brs, uint64_t* kss,
                                       uint32_t* levels) {
   if (!shape) return VLP_EINVAL;
@@ -665,49 +739,29 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
       return fail(ctx, VLP_EINVAL, "an output overlaps an input");
   }
 
-  // Output slots: v of record i -> v_out[i] (if given); R[j] -> R[j].
-  std::vector<int32_t> slot(nl.gates.size(), -1);
-  if (v_out_dev)
-    for (size_t i = 0; i < M; ++i)
-      if (nl.v_of_record[i].src == Src::Gate) slot[nl.v_of_record[i].index] = (int32_t)i;
-  for (size_t j = 0; j < lS; ++j) {
-    const Operand& r = nl.result[j];
-    if (r.src != Src::Gate || slot[r.index] >= 0)
-      return fail(ctx, VLP_EINVAL, "unsupported shape: result bit %zu is not a distinct gate", j);
-    slot[r.index] = (int32_t)(M + j);
-  }
-  // Internal storage for the other gates.
-  std::vector<uint32_t> internal(nl.gates.size(), 0);
-  uint32_t n_internal = 0;
-  for (size_t g = 0; g < nl.gates.size(); ++g)
-    if (slot[g] < 0) internal[g] = n_internal++;
-
-  // Gates by level.
+  // Output slots: v of record i -> v_out[i] (if given); R[j] -> R[j]; other gates internal.
+  ProgramSizes z;
+  if (const char* bad = program_sizes(nl, v_out_dev != nullptr, z))
+    return fail(ctx, VLP_EINVAL, "unsupported shape: %s", bad);
+  const std::vector<int32_t>& slot = z.slot;
+  const std::vector<uint32_t>& internal = z.internal;
   std::vector<std::vector<uint32_t>> by_level(nl.levels + 1);
   for (size_t g = 0; g < nl.gates.size(); ++g) by_level[nl.gates[g].level].push_back((uint32_t)g);
-  uint32_t max_br = 0, max_ks = 0;
-  for (uint32_t L = 1; L <= nl.levels; ++L) {
-    uint32_t nbr = 0;
-    for (uint32_t g : by_level[L]) nbr += nl.gates[g].op == VLP_MUX ? 2 : 1;
-    max_br = std::max(max_br, nbr);
-    max_ks = std::max(max_ks, (uint32_t)by_level[L].size());
+  const uint64_t n_br = z.n_br, n_ks = z.n_ks;
+  const size_t n_more = z.n_more;
+  const size_t b_items = z.b_items, k_items = z.k_items, b_gate = z.b_gate, b_ext = z.b_ext, b_more = z.b_more,
+               b_dig = z.b_dig, total = z.total;
+  // The merged-step scratch grows with the reserve at creation (vlp_step never allocates).
+  const size_t new_reserve = ctx->step_reserve + z.step;
+  const size_t grow = new_reserve > ctx->scratch_bytes ? new_reserve : 0;
+  if (ctx->used + total + (grow ? grow - ctx->scratch_bytes : 0) > ctx->budget)
+    return fail(ctx, VLP_EBUDGET, "program needs %zu bytes (+%zu of step scratch); %zu of %zu in use", total,
+                grow ? grow - ctx->scratch_bytes : 0, ctx->used, ctx->budget);
+  if (grow) {
+    vlp_status gst = ensure_scratch(ctx, grow);
+    if (gst != VLP_OK) return gst;
   }
-  const uint64_t n_br = nl.blind_rotations(), n_ks = nl.key_switches();
-  // Operand-list entries of the k-input XORs: the non-trivial operands past the first two.
-  size_t n_more = 0;
-  for (const Gate& G : nl.gates) {
-    if (G.op != OP_XORK) continue;
-    size_t live = (G.a.is_const() ? 0 : 1) + (G.b.is_const() ? 0 : 1);
-    for (uint32_t t = 0; t < G.xk_count; ++t) live += nl.xk_ops[G.xk_first + t].is_const() ? 0 : 1;
-    n_more += live > 2 ? live - 2 : 0;
-  }
-  const size_t b_items = n_br * sizeof(BrItem), k_items = n_ks * sizeof(KsItem);
-  const size_t b_gate = (size_t)n_internal * CT_n * 4, b_ext = (size_t)max_br * CT_N * 4;
-  const size_t b_more = n_more * sizeof(const uint32_t*);
-  const size_t b_dig = ks_digit_bytes(max_ks);
-  const size_t total = b_items + k_items + b_gate + b_ext + b_more + b_dig;
-  if (ctx->used + total > ctx->budget)
-    return fail(ctx, VLP_EBUDGET, "program needs %zu bytes; %zu of %zu in use", total, ctx->used, ctx->budget);
+  const uint32_t max_br = z.max_br;
 
   vlp_program* prog = new vlp_program();
   prog->ctx = ctx;
@@ -730,6 +784,7 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   if (e == hipSuccess && b_more) e = hipMalloc((void**)&prog->more_buf, b_more);
   if (e == hipSuccess && b_dig) e = hipMalloc((void**)&prog->dig_buf, b_dig);
   if (e != hipSuccess) {
+    (void)hipGetLastError();
     (void)hipFree(prog->br_items);
     (void)hipFree(prog->ks_items);
     (void)hipFree(prog->gate_buf);
@@ -737,10 +792,13 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
     (void)hipFree(prog->more_buf);
     (void)hipFree(prog->dig_buf);
     delete prog;
-    return fail(ctx, VLP_EHIP, "program allocation: %s", hipGetErrorString(e));
+    return fail(ctx, e == hipErrorOutOfMemory ? VLP_EBUDGET : VLP_EHIP, "program allocation: %s",
+                hipGetErrorString(e));
   }
   prog->bytes = total;
+  prog->step_bytes = z.step;
   ctx->used += total;
+  ctx->step_reserve += z.step;
   ks->users++;
   ctx->live_programs++;
 
@@ -888,6 +946,14 @@ extern "C" vlp_status vlp_program_counts(const vlp_program* prog, uint64_t* gate
   if (brs) *brs = prog->brs;
   if (kss) *kss = prog->kss;
   if (levels) *levels = (uint32_t)prog->levels.size();
+  return VLP_OK;
+}
+
+extern "C" vlp_status vlp_program_level_counts(const vlp_program* prog, uint32_t level, uint64_t* blind_rotations,
+                                               uint64_t* key_switches) {
+  if (!prog || level >= prog->levels.size()) return VLP_EINVAL;
+  if (blind_rotations) *blind_rotations = prog->levels[level].br_count;
+  if (key_switches) *key_switches = prog->levels[level].ks_count;
   return VLP_OK;
 }
 

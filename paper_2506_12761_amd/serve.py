@@ -9,6 +9,12 @@ current circuit level of every active request in one merged batch of kernel
 launches, so a request admitted while others are running joins at the next
 step, and finished requests free their memory for queued ones.
 
+Which admitted requests a step advances is the policy: "all" (every active
+request, one level each) or "srpt" (shortest remaining work first: active
+requests in order of blind rotations left, added while the step's rotations
+stay within a cap, at least one per step), which keeps a small query from
+waiting behind the huge levels of large ones.
+
 The executor is an interface so the scheduling logic can be exercised on a
 CPU with a stand-in executor; GpuExecutor drives libvlp.
 """
@@ -56,6 +62,12 @@ class Executor:
     def levels_left(self, handle) -> int:
         raise NotImplementedError
 
+    def work_left(self, handle) -> int:        # blind rotations left (for the srpt policy)
+        return self.levels_left(handle)
+
+    def next_work(self, handle) -> int:        # blind rotations of the next level
+        return 1
+
     def destroy(self, handle) -> None:
         raise NotImplementedError
 
@@ -63,29 +75,90 @@ class Executor:
         pass
 
 
-class GpuExecutor(Executor):
-    """libvlp programs on one device; keysets[client] must already be loaded."""
+KEYSET_BYTES = 61931520 + 83886080  # transformed bootstrapping key + key-switching byte planes
 
-    def __init__(self, ctx, keysets: dict):
+
+class GpuExecutor(Executor):
+    """libvlp programs on one device.
+
+    keysets[client] may be loaded beforehand; otherwise key_factory(client)
+    returns the client's (bk, ksk) device tensors, loaded at admission and
+    dropped when the client has no request left.  input_factory(req), if
+    given, returns the request's payload of device buffers (query, db_loc,
+    db_pay, R, v), allocated at admission and released at destruction.  With
+    `budget` (bytes), a request is admitted only while the library's memory,
+    the resident keys and the held input buffers, plus what the request would
+    add (its program by vlp_plan_bytes, its inputs, its keys), fit."""
+
+    def __init__(self, ctx, keysets: dict | None = None, key_factory=None, input_factory=None,
+                 budget: int | None = None):
         from . import vlp
         self.vlp = vlp
         self.ctx = ctx
-        self.keysets = keysets
+        self.keysets = dict(keysets or {})
+        self.key_factory = key_factory
+        self.input_factory = input_factory
+        self.budget = budget
         self._left = {}
+        self._levels = {}
+        self._req = {}
+        self._users = {}
+        self.input_bytes = 0
+
+    @staticmethod
+    def _input_bytes(req: Request) -> int:
+        d = req.d if req.mode != "idm" else 1
+        loc = req.M * d * (2 if req.mode == "intv" else 1) * req.l_I
+        return 631 * 4 * (d * req.l_I + loc + 2 * req.M * req.l_S + req.l_S + req.M)
+
+    def held(self) -> int:
+        """Device bytes held: the library's (programs, keysets, scratch) and the inputs."""
+        return self.vlp.vlp_mem_info(self.ctx.ctx)[0] + self.input_bytes
 
     def create(self, req: Request):
         v = self.vlp
-        p = req.payload
         shape = v.make_shape(req.mode, req.M, req.l_I, req.l_S, req.d)
+        new_keys = req.client not in self.keysets
+        in_bytes = self._input_bytes(req) if self.input_factory else 0
+        if self.budget is not None:
+            need = v.vlp_plan_bytes(shape, True) + in_bytes + (KEYSET_BYTES if new_keys else 0)
+            if self.held() + need > self.budget:
+                raise BudgetExceeded("request %d needs %d bytes; %d of %d held" % (req.rid, need, self.held(),
+                                                                                  self.budget))
+        if new_keys:
+            bk, ksk = self.key_factory(req.client)
+            self.keysets[req.client] = self.ctx.load_keys(bk, ksk)
+            del bk, ksk
+        if self.input_factory:
+            req.payload = self.input_factory(req)
+            self.input_bytes += in_bytes
+        p = req.payload
         try:
             h = v.vlp_program_create(self.ctx.ctx, self.keysets[req.client], shape, p["query"], p["db_loc"],
                                      p.get("db_pay"), p.get("R"), p.get("v"))
         except v.VlpError as e:
+            self._release(req, in_bytes, new_keys)
             if e.status == v.VLP_EBUDGET:
                 raise BudgetExceeded(str(e)) from None
             raise
-        self._left[h] = v.vlp_program_counts(self.ctx.ctx, h)["levels"]
+        n = v.vlp_program_counts(self.ctx.ctx, h)["levels"]
+        self._levels[h] = [v.vlp_program_level_counts(self.ctx.ctx, h, L)["blind_rotations"] for L in range(n)]
+        self._left[h] = n
+        self._req[h] = (req, in_bytes)
+        self._users[req.client] = self._users.get(req.client, 0) + 1
         return h
+
+    def _release(self, req: Request, in_bytes: int, drop_keys: bool) -> None:
+        if self.input_factory:
+            kept = {"R_host": req.payload["R_host"]} if "R_host" in req.payload else {}
+            req.payload = kept
+            self.input_bytes -= in_bytes
+        if drop_keys and self.key_factory and req.client in self.keysets:
+            self.ctx.drop_keys(self.keysets.pop(req.client))
+        if self.input_factory or self.key_factory:
+            # Freed tensors go back to the device, not to torch's cache, so the
+            # library's own allocations can use the memory.
+            self.ctx.torch.cuda.empty_cache()
 
     def step(self, handles):
         if not handles:
@@ -99,27 +172,57 @@ class GpuExecutor(Executor):
     def levels_left(self, handle) -> int:
         return self._left[handle]
 
+    def work_left(self, handle) -> int:
+        lv = self._levels[handle]
+        return sum(lv[len(lv) - self._left[handle]:])
+
+    def next_work(self, handle) -> int:
+        lv = self._levels[handle]
+        return lv[len(lv) - self._left[handle]] if self._left[handle] else 0
+
     def destroy(self, handle):
         self._left.pop(handle, None)
+        self._levels.pop(handle, None)
         self.vlp.vlp_program_destroy(self.ctx.ctx, handle)
+        req, in_bytes = self._req.pop(handle)
+        self._users[req.client] -= 1
+        self._release(req, in_bytes, self._users[req.client] == 0)
 
     def fetch(self, req):
         R = req.payload.get("R")
         req.payload["R_host"] = self.ctx.to_host(R).copy() if R is not None else None
 
 
+def select_step(active: list, executor: Executor, policy: str, step_cap: int | None) -> list:
+    """The active requests a step advances (see the module docstring)."""
+    if policy == "all":
+        return list(active)
+    if policy != "srpt":
+        raise ValueError("unknown policy %r" % policy)
+    order = sorted(active, key=lambda r: (executor.work_left(r.handle), r.arrival, r.rid))
+    chosen, total = [], 0
+    for r in order:
+        w = executor.next_work(r.handle)
+        if chosen and step_cap is not None and total + w > step_cap:
+            continue
+        chosen.append(r)
+        total += w
+    return chosen
+
+
 def serve(requests: list[Request], executor: Executor, max_active: int | None = None,
-          clock=time.perf_counter, sleep=time.sleep, log=None) -> dict:
+          clock=time.perf_counter, sleep=time.sleep, log=None, policy: str = "all",
+          step_cap: int | None = None) -> dict:
     """Run the request stream to completion; returns latency statistics.
 
     Arrival times are offsets from the start.  A request is admitted at the
     first step boundary after its arrival at which the executor accepts it
-    (arrival order, no overtaking); each step advances every admitted,
-    unfinished request by one circuit level.  A request's latency runs from
-    its arrival to its result copied to the host.  A request whose cancel_at
-    has passed is dropped at the next step boundary: never admitted if still
-    queued, otherwise its program is destroyed and its memory freed for the
-    queue."""
+    (arrival order, no overtaking); each step advances the admitted requests
+    the policy selects by one circuit level each.  A request's latency runs
+    from its arrival to its result copied to the host.  A request whose
+    cancel_at has passed is dropped at the next step boundary: never admitted
+    if still queued, otherwise its program is destroyed and its memory freed
+    for the queue."""
     pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
     waiting: list[Request] = []
     active: list[Request] = []
@@ -163,7 +266,7 @@ def serve(requests: list[Request], executor: Executor, max_active: int | None = 
             if waiting:
                 raise RuntimeError("request %d cannot be admitted even on an idle device" % waiting[0].rid)
             continue
-        executor.step([r.handle for r in active])
+        executor.step([r.handle for r in select_step(active, executor, policy, step_cap)])
         steps += 1
         max_active_seen = max(max_active_seen, len(active))
         still = []
@@ -182,6 +285,8 @@ def serve(requests: list[Request], executor: Executor, max_active: int | None = 
     wall = clock() - t0
     lat = sorted(r.latency for r in done)
     return {
+        "policy": policy,
+        "step_cap": step_cap,
         "queries": len(done),
         "wall_s": wall,
         "queries_per_s": len(done) / wall if wall > 0 else None,

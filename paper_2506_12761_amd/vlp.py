@@ -32,7 +32,7 @@ EXPORTS = [
     "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_gate_noalloc",
     "vlp_evaluate", "vlp_server_encrypt",
     "vlp_program_create", "vlp_program_reset", "vlp_step", "vlp_program_run", "vlp_program_counts",
-    "vlp_plan_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
+    "vlp_plan_counts", "vlp_plan_bytes", "vlp_program_level_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
     "vlp_profile_enable", "vlp_profile_read", "vlp_measure_modmul_peak",
 ]
 
@@ -95,6 +95,8 @@ def lib():
             "vlp_program_run": (ctypes.c_int, [vp, vp, ctypes.c_int]),
             "vlp_program_counts": (ctypes.c_int, [vp, P(u64), P(u64), P(u64), P(u32)]),
             "vlp_plan_counts": (ctypes.c_int, [P(vlp_shape), P(u64), P(u64), P(u64), P(u32)]),
+            "vlp_plan_bytes": (ctypes.c_int, [P(vlp_shape), ctypes.c_int, P(sz)]),
+            "vlp_program_level_counts": (ctypes.c_int, [vp, u32, P(u64), P(u64)]),
             "vlp_program_destroy": (ctypes.c_int, [vp]),
             "vlp_get_tuning": (ctypes.c_int, [vp, P(vlp_tuning)]),
             "vlp_set_tuning": (ctypes.c_int, [vp, P(vlp_tuning)]),
@@ -247,6 +249,20 @@ def vlp_plan_counts(shape: vlp_shape) -> dict:
     if st != VLP_OK:
         raise VlpError(st, "bad shape")
     return {"gates": g.value, "blind_rotations": b.value, "key_switches": k.value, "levels": l.value}
+
+
+def vlp_plan_bytes(shape: vlp_shape, with_v_out: bool = True) -> int:
+    b = ctypes.c_size_t()
+    st = lib().vlp_plan_bytes(ctypes.byref(shape), 1 if with_v_out else 0, ctypes.byref(b))
+    if st != VLP_OK:
+        raise VlpError(st, "bad shape")
+    return b.value
+
+
+def vlp_program_level_counts(ctx, prog, level: int) -> dict:
+    b, k = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, lib().vlp_program_level_counts(prog, level, ctypes.byref(b), ctypes.byref(k)))
+    return {"blind_rotations": b.value, "key_switches": k.value}
 
 
 def vlp_program_destroy(ctx, prog) -> None:

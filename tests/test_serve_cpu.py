@@ -125,3 +125,74 @@ def test_cancel_after_finish_is_a_noop():
     reqs[0].cancel_at = 50.0
     st = serve(reqs, ex, clock=clk, sleep=clk.sleep)
     assert st["queries"] == 1 and st["cancelled"] == 0 and reqs[0].cancelled is None
+
+
+class WorkExecutor(FakeExecutor):
+    """Programs whose levels have a rotation count (M per level); a step costs
+    its merged rotations x step_s / 1000 seconds, like the device."""
+
+    def create(self, req):
+        h = super().create(req)
+        self.work = getattr(self, "work", {})
+        self.work[h] = [req.M] * LEVELS[req.mode]
+        return h
+
+    def work_left(self, h):
+        return sum(self.work[h][len(self.work[h]) - self.left[h]:])
+
+    def next_work(self, h):
+        return self.work[h][len(self.work[h]) - self.left[h]] if self.left[h] else 0
+
+    def step(self, handles):
+        rot = sum(self.next_work(h) for h in handles)
+        self.rot_log = getattr(self, "rot_log", []) + [(len(handles), rot)]
+        super().step(handles)
+        self.clock.t += rot * self.step_s / 1000 - self.step_s
+
+
+def test_srpt_policy_lets_small_queries_pass_a_large_one():
+    """Shortest remaining work first with a rotation cap per step: a small
+    query arriving while a large one runs finishes far sooner than under
+    the merge-all policy, and the large one still completes; every step
+    advances at least one query and respects the cap unless one level alone
+    exceeds it."""
+    spec = [("idm", 4000, 0.0), ("cov", 10, 0.5), ("cov", 10, 0.6)]
+    res = {}
+    for policy in ("all", "srpt"):
+        clk = FakeClock()
+        ex = WorkExecutor(clk, budget=10_000)
+        st = serve(_reqs(spec), ex, clock=clk, sleep=clk.sleep, policy=policy, step_cap=100)
+        assert st["queries"] == 3 and st["policy"] == policy
+        res[policy] = {r.rid: r.latency for r in st["requests"]}
+        assert all(len(s) >= 1 for s in ex.step_log)
+        if policy == "srpt":
+            assert all(n == 1 or rot <= 100 for n, rot in ex.rot_log)
+            assert any(n == 1 and rot > 100 for n, rot in ex.rot_log)  # the large level runs alone
+    assert res["srpt"][1] < 0.2 * res["all"][1] and res["srpt"][2] < 0.2 * res["all"][2]
+    assert res["srpt"][0] <= res["all"][0] + 0.5  # the large query loses little
+
+
+def test_srpt_selection_order_and_cap():
+    from paper_2506_12761_amd.serve import select_step
+
+    class Ex(FakeExecutor):
+        def __init__(self):
+            pass
+
+        def work_left(self, h):
+            return {1: 500, 2: 50, 3: 80, 4: 5000}[h]
+
+        def next_work(self, h):
+            return {1: 100, 2: 10, 3: 60, 4: 900}[h]
+
+    reqs = _reqs([("idm", 1, 0.0), ("idm", 1, 0.0), ("idm", 1, 0.0), ("idm", 1, 0.0)])
+    for h, r in zip((1, 2, 3, 4), reqs):
+        r.handle = h
+    pick = lambda cap: [r.handle for r in select_step(reqs, Ex(), "srpt", cap)]
+    assert pick(None) == [2, 3, 1, 4]          # no cap: all, least remaining work first
+    assert pick(100) == [2, 3]                 # 10 + 60; 100 more would pass the cap
+    assert pick(200) == [2, 3, 1]
+    assert pick(5) == [2]                      # always at least one
+    assert [r.handle for r in select_step(reqs, Ex(), "all", 5)] == [1, 2, 3, 4]
+    with pytest.raises(ValueError):
+        select_step(reqs, Ex(), "fastest", None)
