@@ -203,6 +203,27 @@ def decrypt(keys: Keys, ct) -> np.ndarray:
     return (phase(keys, ct).astype(np.int64) < 2**31).astype(np.uint8)
 
 
+# Decryption is correct while a ciphertext's noise stays below 1/16 of the
+# torus (Section 2.2; a gate's input is the sum of two ciphertexts, whose
+# noise must stay below the 1/8 distance between the encodings and 0).
+NOISE_BUDGET = 1 << 28  # 1/16 as a torus32 word
+
+
+def noise_of(keys: Keys, ct) -> np.ndarray:
+    """Signed noise of ciphertexts (int64 words): the phase, centred, minus the
+    nearer of the two encodings +-1/8."""
+    ph = phase(keys, ct).astype(np.int64)
+    ph = np.where(ph >= 2**31, ph - 2**32, ph)
+    return np.where(ph >= 0, ph - MU, ph + MU)
+
+
+def decrypt_checked(keys: Keys, ct) -> tuple[np.ndarray, np.ndarray]:
+    """(bits, ok): the decrypted bits, and ok = False wherever the noise has
+    reached the 1/16 budget -- there the phase lies within 1/16 of a decision
+    boundary (0 or 1/2) and the bit may be wrong."""
+    return decrypt(keys, ct), np.abs(noise_of(keys, ct)) < NOISE_BUDGET
+
+
 # ----------------------------------------------------------------------------
 # Bootstrapping and gates
 # ----------------------------------------------------------------------------

@@ -258,7 +258,7 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
 // of the workgroup meets the same barriers.
 template <int PR, bool SKIP>
 __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const uint16_t* abar, uint32_t* buf,
-                                           const uint32_t* other_buf, const uint2* tws, const uint2* gtw2, int lane) {
+                                           const uint32_t* other_buf, const uint2* tws, int lane) {
   constexpr uint32_t P = Prime<PR>::P, PINV = Prime<PR>::PINV;
   const uint32_t* bk_i = I.bk;
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
@@ -272,20 +272,19 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     for (int r = 0; r < 16; ++r) m0[r] = m1[r] = 0;
 #pragma unroll 1
     for (int c = 0; c < 2; ++c) {
-      const uint32_t* poly = acc + c * RING_N;
+      // Polynomial c and its negation side by side (2048 words): coefficient
+      // j of X^ab p is word (j - ab) mod 2048 of that window.
+      const uint32_t* poly = acc + c * 2 * RING_N;
       uint32_t D[16], src[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const uint32_t j = r * 64 + lane;
-        src[r] = poly[((j + 2048u - ab) & 2047u) & 1023u];  // coefficient j of X^ab p is +-p[j - ab]
+        src[r] = poly[(j + 2048u - ab) & 2047u];
         D[r] = poly[j];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
-        D[r] = ((s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET) ^ DIGIT_FLIP;
-      }
+      for (int r = 0; r < 16; ++r) D[r] = (src[r] - D[r] + DEC_OFFSET) ^ DIGIT_FLIP;
 #pragma unroll 1
       for (int lev = 0; lev < ELL; ++lev) {
         // This prime's planes of the two key rows of the digit, requested
@@ -301,7 +300,7 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
         uint32_t x[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = digit_of(D[r], shift);  // balanced digit, signed
-        ntt_fwd1<PR>(x, buf, tws, gtw2, lane);
+        ntt_fwd1<PR>(x, buf, tws, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           m0[r] += (int64_t)(int32_t)x[r] * (int32_t)b0[r];
@@ -316,18 +315,18 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     uint32_t keep[16], x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = redc_s(KEEP ? m1[r] : m0[r], P, PINV);
-    ntt_inv1<PR>(x, buf, tws, gtw2, lane);
+    ntt_inv1<PR>(x, buf, tws, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       keep[r] = x[r];  // in (-P/2, 3P/2): the lift takes lazy residues
       x[r] = redc_s(KEEP ? m0[r] : m1[r], P, PINV);
     }
-    ntt_inv1<PR>(x, buf, tws, gtw2, lane);
+    ntt_inv1<PR>(x, buf, tws, lane);
     wave_lds_sync();  // the transform's last reads of buf are done
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[r * 64 + lane] = x[r];
     __syncthreads();  // both wavefronts have parked their residues
-    uint32_t* poly = acc + KEEP * RING_N;
+    uint32_t* poly = acc + KEEP * 2 * RING_N;
     uint32_t old[16], oth[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -336,8 +335,11 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      poly[r * 64 + lane] = old[r] + (PR == 0 ? crt_lift_s(keep[r], oth[r]) : crt_lift_s(oth[r], keep[r]));
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t v = old[r] + (PR == 0 ? crt_lift_s(keep[r], oth[r]) : crt_lift_s(oth[r], keep[r]));
+      poly[r * 64 + lane] = v;
+      poly[RING_N + r * 64 + lane] = 0u - v;
+    }
     __syncthreads();  // accumulator updated; parked residues consumed
   }
 }
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) 
     const BrItem* __restrict__ items, uint32_t count, const Tw* __restrict__ tw_fwd) {
   __shared__ uint2 s_tw[2][RING_N];              // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
   __shared__ __align__(16) uint32_t s_buf[2 * ROT][RING_N];  // per wavefront: transpose scratch, then parked residues
-  __shared__ uint32_t s_acc[ROT][2][RING_N];     // per rotation: accumulator (A, B), coefficient order
+  __shared__ uint32_t s_acc[ROT][2][2 * RING_N];  // per rotation: accumulator A, -A, B, -B, coefficient order
   __shared__ uint16_t s_abar[ROT][CT_n + 1];     // per rotation: modulus-switched input
   for (int e = 16 + threadIdx.x; e < RING_N; e += blockDim.x) {  // stages 4..9 (entries 16..1023)
     const int S = 31 - __builtin_clz(e);
@@ -368,7 +370,6 @@ __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) 
   // Raising the first one's issue priority lets it run ahead until it waits
   // while the other fills the gaps (12.21 -> 12.12 ms per launch).
   if (ROT == 4 && rot_i < 2) __builtin_amdgcn_s_setprio(1);
-  const uint2* gtw2 = reinterpret_cast<const uint2*>(tw_fwd);
   uint32_t* acc = s_acc[rot_i][0];
   uint16_t* abar = s_abar[rot_i];
   for (uint32_t g = blockIdx.x; g * ROT < count; g += gridDim.x) {
@@ -393,22 +394,20 @@ __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) 
     for (int r = 0; r < 16; ++r) {
       const uint32_t j = r * 64 + lane;
       const bool neg = (j < (rot & 1023u)) != (rot >= 1024u);
-      acc[pr * RING_N + j] = pr == 0 ? 0u : (neg ? (0u - I.mu) : I.mu);
+      const uint32_t v = pr == 0 ? 0u : (neg ? (0u - I.mu) : I.mu);
+      acc[pr * 2 * RING_N + j] = v;
+      acc[pr * 2 * RING_N + RING_N + j] = 0u - v;
     }
     __syncthreads();
     if (pr == 0)
-      br2_rotate<0, ROT == 1>(I, acc, abar, s_buf[2 * rot_i], s_buf[2 * rot_i + 1], s_tw[0], gtw2, lane);
+      br2_rotate<0, ROT == 1>(I, acc, abar, s_buf[2 * rot_i], s_buf[2 * rot_i + 1], s_tw[0], lane);
     else
-      br2_rotate<1, ROT == 1>(I, acc, abar, s_buf[2 * rot_i + 1], s_buf[2 * rot_i], s_tw[1], gtw2, lane);
+      br2_rotate<1, ROT == 1>(I, acc, abar, s_buf[2 * rot_i + 1], s_buf[2 * rot_i], s_tw[1], lane);
     // SampleExtract: a'_0 = A_0, a'_j = -A_(N-j), b' = B_0 (the last update is
     // visible after the rotation's closing barrier, or the one above if no step ran).
     if (active) {
-      for (int j = t; j < RING_N; j += 128) {
-        const uint32_t a = acc[j];
-        if (j == 0) I.out[0] = a;
-        else I.out[RING_N - j] = 0u - a;
-      }
-      if (t == 0) I.out[RING_N] = acc[RING_N];
+      for (int j = t; j < RING_N; j += 128) I.out[j] = j == 0 ? acc[0] : acc[2 * RING_N - j];  // -A_(N-j)
+      if (t == 0) I.out[RING_N] = acc[2 * RING_N];
     }
   }
 }
@@ -430,7 +429,7 @@ __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) 
 template <int PR, int H>
 __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const uint16_t* abar, uint32_t* buf,
                                            const uint32_t* prime_partner_buf, uint32_t* xbuf,
-                                           const uint32_t* half_partner_xbuf, const uint2* tws, const uint2* gtw2,
+                                           const uint32_t* half_partner_xbuf, const uint2* tws,
                                            int lane) {
   constexpr uint32_t P = Prime<PR>::P, PINV = Prime<PR>::PINV;
   const uint32_t* bk_i = I.bk;
@@ -470,7 +469,7 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
         uint32_t x[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) x[r] = digit_of(D[r], shift);  // balanced digit, signed
-        ntt_fwd1<PR>(x, buf, tws, gtw2, lane);
+        ntt_fwd1<PR>(x, buf, tws, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           m0[r] += (int64_t)(int32_t)x[r] * (int32_t)b0[r];
@@ -492,7 +491,7 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] += oth[r];  // (-4P, 4P)
-    ntt_inv1<PR>(x, buf, tws, gtw2, lane);
+    ntt_inv1<PR>(x, buf, tws, lane);
     // Wave (0, H) lifts registers 0..7, wave (1, H) registers 8..15: each parks
     // the half the other one lifts.
     wave_lds_sync();  // the transform's last reads of buf are done
@@ -533,7 +532,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint2* gtw2 = reinterpret_cast<const uint2*>(tw_fwd);
   uint32_t* acc = s_acc[0];
   for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
     const BrItem I = items[it];
@@ -559,10 +557,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     }
     __syncthreads();
     switch (wave) {
-      case 0: br4_rotate<0, 0>(I, acc, s_abar, s_buf[0], s_buf[1], s_x[0], s_x[2], s_tw[0], gtw2, lane); break;
-      case 1: br4_rotate<1, 0>(I, acc, s_abar, s_buf[1], s_buf[0], s_x[1], s_x[3], s_tw[1], gtw2, lane); break;
-      case 2: br4_rotate<0, 1>(I, acc, s_abar, s_buf[2], s_buf[3], s_x[2], s_x[0], s_tw[0], gtw2, lane); break;
-      default: br4_rotate<1, 1>(I, acc, s_abar, s_buf[3], s_buf[2], s_x[3], s_x[1], s_tw[1], gtw2, lane); break;
+      case 0: br4_rotate<0, 0>(I, acc, s_abar, s_buf[0], s_buf[1], s_x[0], s_x[2], s_tw[0], lane); break;
+      case 1: br4_rotate<1, 0>(I, acc, s_abar, s_buf[1], s_buf[0], s_x[1], s_x[3], s_tw[1], lane); break;
+      case 2: br4_rotate<0, 1>(I, acc, s_abar, s_buf[2], s_buf[3], s_x[2], s_x[0], s_tw[0], lane); break;
+      default: br4_rotate<1, 1>(I, acc, s_abar, s_buf[3], s_buf[2], s_x[3], s_x[1], s_tw[1], lane); break;
     }
     for (int j = threadIdx.x; j < RING_N; j += 256) {
       const uint32_t a = acc[j];

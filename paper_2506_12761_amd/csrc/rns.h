@@ -60,6 +60,59 @@ static_assert((P1 - 1) % 2048 == 0 && (P2 - 1) % 2048 == 0, "primes need 2048-th
 static_assert(Q / 2 > (6ull * 1024 * 64) << 32, "modulus too small for an exact lift");
 static_assert(P2 < P1 && 2 * (uint64_t)P1 < 3 * (uint64_t)P2, "CRT difference range");
 
+// Twiddles: psi_p, the 2048-th root of unity g^((p-1)/2048) of the smallest
+// generator g mod p; entry m is psi_p^brv10(m) as its signed representative
+// w in (-p/2, p/2) with floor(w 2^32 / p) (rounded down for negative w).  The
+// host table (twiddles.cpp) and the kernels' compile-time constants of the
+// first four stages both come from these.
+constexpr uint32_t brv10(uint32_t x) {
+  uint32_t r = 0;
+  for (int i = 0; i < 10; ++i) r |= ((x >> i) & 1u) << (9 - i);
+  return r;
+}
+constexpr uint64_t smallest_generator(uint64_t p) {
+  uint64_t f[16] = {};
+  int nf = 0;
+  uint64_t n = p - 1;
+  for (uint64_t d = 2; d * d <= n; ++d)
+    if (n % d == 0) {
+      f[nf++] = d;
+      while (n % d == 0) n /= d;
+    }
+  if (n > 1) f[nf++] = n;
+  for (uint64_t g = 2;; ++g) {
+    bool ok = true;
+    for (int i = 0; i < nf; ++i) ok = ok && pow_mod(g, (p - 1) / f[i], p) != 1;
+    if (ok) return g;
+  }
+}
+constexpr uint64_t root_2048(uint64_t p) { return pow_mod(smallest_generator(p), (p - 1) / 2048, p); }
+struct TwPair {
+  uint32_t w, q;  // signed twiddle and its signed Shoup quotient, as words
+};
+constexpr TwPair twiddle(uint64_t p, uint64_t psi, uint32_t m) {
+  const int64_t w0 = (int64_t)pow_mod(psi, brv10(m), p);
+  const int64_t w = w0 > (int64_t)p / 2 ? w0 - (int64_t)p : w0;
+  const int64_t n = w * ((int64_t)1 << 32);
+  const int64_t q = n / (int64_t)p - ((n % (int64_t)p != 0 && n < 0) ? 1 : 0);
+  return TwPair{(uint32_t)(int32_t)w, (uint32_t)(int32_t)q};
+}
+constexpr uint64_t PSI1 = root_2048(P1), PSI2 = root_2048(P2);
+static_assert(pow_mod(PSI1, 1024, P1) == P1 - 1 && pow_mod(PSI2, 1024, P2) == P2 - 1, "psi of order 2048");
+
+// Entries 0..15 of each prime's table (the twiddles of stages 0..3).
+struct TwHead {
+  TwPair e[2][16];
+};
+constexpr TwHead make_tw_head() {
+  TwHead t{};
+  for (uint32_t m = 0; m < 16; ++m) {
+    t.e[0][m] = twiddle(P1, PSI1, m);
+    t.e[1][m] = twiddle(P2, PSI2, m);
+  }
+  return t;
+}
+
 // Shoup product, unsigned: y * w mod p in [0, 2p), for y < 2^32, w < p,
 // wp = floor(w 2^32 / p).
 __device__ __forceinline__ uint32_t shoup(uint32_t y, uint32_t w, uint32_t wp, uint32_t p) {
@@ -107,16 +160,24 @@ static_assert(((unsigned __int128)48 * P1 * P1 >> 32) + 1 + P1 < 2ull * P1 &&
                   ((unsigned __int128)48 * P2 * P2 >> 32) + 1 + P2 < 2ull * P2,
               "accumulator range (three products)");
 
+// C12 as a signed representative (|C12S| < P2/2) with its signed Shoup quotient.
+constexpr int64_t C12S = C12 > P2 / 2 ? (int64_t)C12 - P2 : (int64_t)C12;
+constexpr int64_t C12S_Q = (C12S * ((int64_t)1 << 32) - ((C12S * ((int64_t)1 << 32)) % P2 + P2) % P2) / P2;
+
 // Low 32 bits of the centred lift of (x1 mod P1, x2 mod P2) for signed
-// residues x1 in (-P1, 2 P1) and x2 in (-P2, 2 P2).  h = (x2 - x1) P1^-1 mod P2
-// is made canonical; x = x1 + P1 h is then in (-P1, Q + P1) and congruent to
-// the centred integer X (|X| < Q/2) mod Q, so it is X or X + Q, the latter
-// exactly when x > Q/2.
+// residues x1 in (-P1, 2 P1) and x2 in (-P2, 2 P2).  With
+// h = (x2 - x1) P1^-1 mod P2 taken in (-P2/2, 3 P2/2) (one signed Shoup
+// product), the integer X (|X| < 6 * 1024 * 64 * 2^32 < 0.37513 Q) is
+// x1 + P1 h, or that minus Q: in the first case h < 0.37513 P2 + 1, in the
+// second h > 0.62487 P2 - 2, so h > P2/2 tells them apart and only the low
+// words are needed.
+static_assert((6.0 * 1024 * 64 * 4294967296.0) / ((double)P1 * (double)P2) < 0.37513 &&
+                  0.37513 * P2 + 1 < P2 / 2 && 0.62487 * P2 - 2 > P2 / 2,
+              "CRT lift decision range");
 __device__ __forceinline__ uint32_t crt_lift_s(uint32_t x1, uint32_t x2) {
-  const uint32_t d = x2 - x1 + 4u * P2;                      // = x2 - x1 (mod P2), in (0, 7 P2)
-  const uint32_t h = csub(shoup(d, C12, C12_SHOUP, P2), P2);  // [0, P2)
-  const int64_t x = (int64_t)P1 * h + (int32_t)x1;
-  return (uint32_t)x - (x > (int64_t)(Q / 2) ? (uint32_t)Q : 0u);
+  const uint32_t h = shoup_s(x2 - x1, (uint32_t)(int32_t)C12S, (uint32_t)(int32_t)C12S_Q, P2);
+  const uint32_t lo = h * P1 + x1;
+  return (int32_t)h > (int32_t)(P2 / 2) ? lo - (uint32_t)Q : lo;
 }
 
 }  // namespace vlp

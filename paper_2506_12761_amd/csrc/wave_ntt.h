@@ -28,6 +28,8 @@
 // Z differ only in two exchanged bit pairs, which the lane-swap instructions
 // move in registers (swap_yz).
 #pragma once
+#include <type_traits>
+
 #include "rns.h"
 
 namespace vlp {
@@ -291,75 +293,110 @@ __host__ __device__ __forceinline__ constexpr int tw_perm(int S, int o) {
                   : (((o & 7) << 6) | (((o >> 3) & 3) << 4) | ((o >> 5) & 15));     // o = a | h | c (3 bits)
 }
 
-// Stages 0..3 read the global table (wavefront-uniform: scalar loads), entry
-// e of prime PR at gtw2[2e + PR]; stages 4..9 read this prime's permuted LDS
-// plane tws.
+// Calls f(std::integral_constant<int, k>) for k = 0..7.
+template <class F>
+__device__ __forceinline__ void for8(F&& f) {
+  f(std::integral_constant<int, 0>{});
+  f(std::integral_constant<int, 1>{});
+  f(std::integral_constant<int, 2>{});
+  f(std::integral_constant<int, 3>{});
+  f(std::integral_constant<int, 4>{});
+  f(std::integral_constant<int, 5>{});
+  f(std::integral_constant<int, 6>{});
+  f(std::integral_constant<int, 7>{});
+}
+
+// Signed Shoup product by a compile-time twiddle: the quotient stays a scalar
+// operand of the high multiply (an SGPR constant, no vector register copy).
+template <uint32_t W, uint32_t WQ, uint32_t P>
+__device__ __forceinline__ uint32_t shoup_c(uint32_t y) {
+  uint32_t q;
+  asm("v_mul_hi_i32 %0, %1, %2" : "=v"(q) : "v"(y), "s"(WQ));
+  return W * y - q * P;
+}
+
+// Stages 0..3 work in layout A (j = 64 r + lane), where entry 2^S + (j >> (10 - S))
+// = 2^S + (r >> (4 - S)) depends only on the register: the twiddles are
+// compile-time constants.  Stages 4..9 read this prime's permuted LDS plane tws.
 template <int PR, int S, int (*LAY)(int, int), int RB>
-__device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tws, const uint2* gtw2, int lane) {
-  uint2 w[8];
+__device__ __forceinline__ void fwd_stage1(uint32_t (&x)[16], const uint2* tws, int lane) {
+  constexpr uint32_t P = Prime<PR>::P;
+  if constexpr (S < 4) {
+    for8([&](auto kc) {
+      constexpr int r = bfly_reg<RB>(decltype(kc)::value);
+      constexpr TwPair c = twiddle(P, PR ? PSI2 : PSI1, (1u << S) + (uint32_t)(r >> (4 - S)));
+      const uint32_t u = x[r], t = shoup_c<c.w, c.q, P>(x[r | (1 << RB)]);
+      x[r] = u + t;
+      x[r | (1 << RB)] = u - t;
+    });
+  } else {
+    uint2 w[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int o = LAY(lane, bfly_reg<RB>(k)) >> (10 - S);
-    w[k] = S < 4 ? gtw2[2 * ((1 << S) + o) + PR] : tws[(1 << S) + tw_perm(S, o)];
-    if (S < 4) vgpr_quotient(w[k].y);
-  }
-  __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < 8; ++k) w[k] = tws[(1 << S) + tw_perm(S, LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int r = bfly_reg<RB>(k);
-    bfly_ct(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
+    for (int k = 0; k < 8; ++k) {
+      const int r = bfly_reg<RB>(k);
+      bfly_ct(x[r], x[r | (1 << RB)], w[k].x, w[k].y, P);
+    }
   }
 }
 template <int PR, int S, int (*LAY)(int, int), int RB>
-__device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tws, const uint2* gtw2, int lane) {
-  uint2 w[8];
+__device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tws, int lane) {
+  constexpr uint32_t P = Prime<PR>::P;
+  if constexpr (S < 4) {
+    for8([&](auto kc) {
+      constexpr int r = bfly_reg<RB>(decltype(kc)::value);
+      constexpr TwPair c = twiddle(P, PR ? PSI2 : PSI1, (2u << S) - 1 - (uint32_t)(r >> (4 - S)));
+      const uint32_t u = x[r], v = x[r | (1 << RB)];
+      x[r] = inv_reduces(S) ? reduce_s(u + v, P) : u + v;
+      x[r | (1 << RB)] = shoup_c<c.w, c.q, P>(v - u);
+    });
+  } else {
+    uint2 w[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int o = (1 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S));  // entry 2^(S+1) - 1 - i
-    w[k] = S < 4 ? gtw2[2 * ((1 << S) + o) + PR] : tws[(1 << S) + tw_perm(S, o)];
-    if (S < 4) vgpr_quotient(w[k].y);
-  }
-  __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < 8; ++k)
+      w[k] = tws[(1 << S) + tw_perm(S, (1 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S)))];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int r = bfly_reg<RB>(k);
-    bfly_gs_neg<inv_bound(S), inv_reduces(S)>(x[r], x[r | (1 << RB)], w[k].x, w[k].y, Prime<PR>::P);
+    for (int k = 0; k < 8; ++k) {
+      const int r = bfly_reg<RB>(k);
+      bfly_gs_neg<inv_bound(S), inv_reduces(S)>(x[r], x[r | (1 << RB)], w[k].x, w[k].y, P);
+    }
   }
 }
 
-// tws: this prime's permuted LDS plane; gtw2: the global table as uint2 pairs.
+// tws: this prime's permuted LDS plane (stages 4..9).
 template <int PR>
-__device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws,
-                                         const uint2* __restrict__ gtw2, int lane) {
-  fwd_stage1<PR, 0, lay_a, 3>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
+__device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws, int lane) {
+  fwd_stage1<PR, 0, lay_a, 3>(x, tws, lane);
+  fwd_stage1<PR, 1, lay_a, 2>(x, tws, lane);
+  fwd_stage1<PR, 2, lay_a, 1>(x, tws, lane);
+  fwd_stage1<PR, 3, lay_a, 0>(x, tws, lane);
   transpose_a_to_y(x, buf, lane);
-  fwd_stage1<PR, 4, lay_y, 3>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 5, lay_y, 2>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 6, lay_y, 1>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 7, lay_y, 0>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 4, lay_y, 3>(x, tws, lane);
+  fwd_stage1<PR, 5, lay_y, 2>(x, tws, lane);
+  fwd_stage1<PR, 6, lay_y, 1>(x, tws, lane);
+  fwd_stage1<PR, 7, lay_y, 0>(x, tws, lane);
   swap_yz(x);  // layout Y -> Z
-  fwd_stage1<PR, 8, lay_z, 3>(x, tws, gtw2, lane);
-  fwd_stage1<PR, 9, lay_z, 2>(x, tws, gtw2, lane);
+  fwd_stage1<PR, 8, lay_z, 3>(x, tws, lane);
+  fwd_stage1<PR, 9, lay_z, 2>(x, tws, lane);
 }
 
 template <int PR>
-__device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws,
-                                         const uint2* __restrict__ gtw2, int lane) {
-  inv_stage1<PR, 9, lay_z, 2>(x, tws, gtw2, lane);
-  inv_stage1<PR, 8, lay_z, 3>(x, tws, gtw2, lane);
+__device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws, int lane) {
+  inv_stage1<PR, 9, lay_z, 2>(x, tws, lane);
+  inv_stage1<PR, 8, lay_z, 3>(x, tws, lane);
   swap_yz(x);  // layout Z -> Y
-  inv_stage1<PR, 7, lay_y, 0>(x, tws, gtw2, lane);
-  inv_stage1<PR, 6, lay_y, 1>(x, tws, gtw2, lane);
-  inv_stage1<PR, 5, lay_y, 2>(x, tws, gtw2, lane);
-  inv_stage1<PR, 4, lay_y, 3>(x, tws, gtw2, lane);
+  inv_stage1<PR, 7, lay_y, 0>(x, tws, lane);
+  inv_stage1<PR, 6, lay_y, 1>(x, tws, lane);
+  inv_stage1<PR, 5, lay_y, 2>(x, tws, lane);
+  inv_stage1<PR, 4, lay_y, 3>(x, tws, lane);
   transpose_y_to_a(x, buf, lane);
-  inv_stage1<PR, 3, lay_a, 0>(x, tws, gtw2, lane);
-  inv_stage1<PR, 2, lay_a, 1>(x, tws, gtw2, lane);
-  inv_stage1<PR, 1, lay_a, 2>(x, tws, gtw2, lane);
-  inv_stage1<PR, 0, lay_a, 3>(x, tws, gtw2, lane);
+  inv_stage1<PR, 3, lay_a, 0>(x, tws, lane);
+  inv_stage1<PR, 2, lay_a, 1>(x, tws, lane);
+  inv_stage1<PR, 1, lay_a, 2>(x, tws, lane);
+  inv_stage1<PR, 0, lay_a, 3>(x, tws, lane);
 }
 
 }  // namespace vlp

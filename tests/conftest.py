@@ -10,7 +10,17 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
-    config.addinivalue_line("markers", "slow: long-running CPU test")
+    config.addinivalue_line("markers", "slow: long-running CPU test (runs only when -m selects 'slow')")
+
+
+def pytest_collection_modifyitems(config, items):
+    """Slow tests run only when the marker expression names them (-m slow)."""
+    if "slow" in (config.getoption("markexpr") or ""):
+        return
+    skip = pytest.mark.skip(reason="slow: select with -m slow")
+    for item in items:
+        if "slow" in item.keywords:
+            item.add_marker(skip)
 
 
 KEY_SEED = 0x5EED0001

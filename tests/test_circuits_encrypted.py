@@ -1,5 +1,6 @@
 """Encrypted circuits through the oracle: decryption equals the plaintext predicate."""
 import numpy as np
+import pytest
 
 from oracle import circuits as C
 from oracle import oracle as O
@@ -39,3 +40,40 @@ def test_interval_8bit_encrypted(oracle_keys):
             inputs[("hi", i)] = ihi[i]
         vals = G.evaluate(K, inputs)
         assert int(O.decrypt(K, vals[v])) == int(lo <= xv < hi), (lo, hi, xv)
+
+
+@pytest.mark.slow
+def test_interval_8bit_encrypted_all_256_values(oracle_keys):
+    """Every 8-bit x (all 256) through the encrypted 49-bootstrap interval
+    circuit against one seeded interval: 256 independent copies of the
+    circuit in one graph (12,544 bootstraps), each decrypting to
+    lo <= x < hi (Theorem 2) and passing the noise check."""
+    K = oracle_keys
+    g = synth.stream(0x5EED0001, "cfg1")
+    a, b = (int(v) for v in synth.signed_ints(g, 2, 8))
+    lo, hi = min(a, b), max(a, b)
+    if lo == hi:
+        hi = lo + 1
+    G = C.GraphBuilder()
+    blo = [G.input(("lo", i)) for i in range(8)]
+    bhi = [G.input(("hi", i)) for i in range(8)]
+    outs = []
+    for xv in range(-128, 128):
+        x = [G.input(("x", xv, i)) for i in range(8)]
+        outs.append(C.intv(G, [x], [(blo, bhi)], 8))
+    assert G.counts()[1] == 49 * 256
+    ilo = _enc_int(K, lo, 8, "lo", 11)
+    ihi = _enc_int(K, hi, 8, "hi", 12)
+    masks, noise = synth.lwe_randomness(13, "x-all", 256 * 8)
+    xb = synth.to_bits(np.arange(-128, 128), 8)                     # [256][8]
+    ix = O.encrypt_bits_np(K, xb, masks, noise)                      # [256][8][631]
+    inputs = {("lo", i): ilo[i] for i in range(8)}
+    inputs.update({("hi", i): ihi[i] for i in range(8)})
+    for k, xv in enumerate(range(-128, 128)):
+        for i in range(8):
+            inputs[("x", xv, i)] = ix[k, i]
+    vals = G.evaluate(K, inputs)
+    got, ok = O.decrypt_checked(K, np.stack([vals[v] for v in outs]))
+    want = np.array([int(lo <= xv < hi) for xv in range(-128, 128)], np.uint8)
+    assert np.array_equal(got, want) and ok.all()
+    assert 0 < want.sum() < 256
