@@ -258,7 +258,7 @@ __global__ __launch_bounds__(64 * WAVES) void br_kernel(const BrItem* __restrict
 // of the workgroup meets the same barriers.
 template <int PR, bool SKIP>
 __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const uint16_t* abar, uint32_t* buf,
-                                           const uint32_t* other_buf, const uint2* tws, int lane) {
+                                           uint32_t* buf2, const uint32_t* other_buf, const uint2* tws, int lane) {
   constexpr uint32_t P = Prime<PR>::P, PINV = Prime<PR>::PINV;
   const uint32_t* bk_i = I.bk;
   for (int i = 0; i < LWE_n; ++i, bk_i += BK_ROW_WORDS) {
@@ -314,14 +314,11 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
     constexpr int KEEP = PR;
     uint32_t keep[16], x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = redc_s(KEEP ? m1[r] : m0[r], P, PINV);
-    ntt_inv1<PR>(x, buf, tws, lane);
-#pragma unroll
     for (int r = 0; r < 16; ++r) {
-      keep[r] = x[r];  // in (-P/2, 3P/2): the lift takes lazy residues
+      keep[r] = redc_s(KEEP ? m1[r] : m0[r], P, PINV);
       x[r] = redc_s(KEEP ? m0[r] : m1[r], P, PINV);
     }
-    ntt_inv1<PR>(x, buf, tws, lane);
+    ntt_inv1_pair<PR>(keep, x, buf, buf2, tws, lane);  // keep ends in (-P/2, 3P/2): the lift takes lazy residues
     wave_lds_sync();  // the transform's last reads of buf are done
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[r * 64 + lane] = x[r];
@@ -353,6 +350,7 @@ __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) 
     const BrItem* __restrict__ items, uint32_t count, const Tw* __restrict__ tw_fwd) {
   __shared__ uint2 s_tw[2][RING_N];              // per prime: {w, Shoup(w)}, stage slices permuted (16 KB)
   __shared__ __align__(16) uint32_t s_buf[2 * ROT][RING_N];  // per wavefront: transpose scratch, then parked residues
+  __shared__ __align__(16) uint32_t s_buf2[2 * ROT][RING_N]; // per wavefront: second transpose scratch
   __shared__ uint32_t s_acc[ROT][2][2 * RING_N];  // per rotation: accumulator A, -A, B, -B, coefficient order
   __shared__ uint16_t s_abar[ROT][CT_n + 1];     // per rotation: modulus-switched input
   for (int e = 16 + threadIdx.x; e < RING_N; e += blockDim.x) {  // stages 4..9 (entries 16..1023)
@@ -400,9 +398,9 @@ __global__ __launch_bounds__(128 * ROT) __attribute__((amdgpu_waves_per_eu(2))) 
     }
     __syncthreads();
     if (pr == 0)
-      br2_rotate<0, ROT == 1>(I, acc, abar, s_buf[2 * rot_i], s_buf[2 * rot_i + 1], s_tw[0], lane);
+      br2_rotate<0, ROT == 1>(I, acc, abar, s_buf[2 * rot_i], s_buf2[2 * rot_i], s_buf[2 * rot_i + 1], s_tw[0], lane);
     else
-      br2_rotate<1, ROT == 1>(I, acc, abar, s_buf[2 * rot_i + 1], s_buf[2 * rot_i], s_tw[1], lane);
+      br2_rotate<1, ROT == 1>(I, acc, abar, s_buf[2 * rot_i + 1], s_buf2[2 * rot_i + 1], s_buf[2 * rot_i], s_tw[1], lane);
     // SampleExtract: a'_0 = A_0, a'_j = -A_(N-j), b' = B_0 (the last update is
     // visible after the rotation's closing barrier, or the one above if no step ran).
     if (active) {

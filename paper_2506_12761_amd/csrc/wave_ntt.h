@@ -399,4 +399,76 @@ __device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const
   inv_stage1<PR, 0, lay_a, 3>(x, tws, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Two inverse transforms of one prime side by side (the two output
+// polynomials of a CMux): every stage reads its twiddles once for both, and
+// the two Y -> A transposes share one LDS round trip (bufx, bufy: the
+// wavefront's two 8-byte-aligned buffers).
+// ---------------------------------------------------------------------------
+template <int PR, int S, int (*LAY)(int, int), int RB>
+__device__ __forceinline__ void inv_stage1_pair(uint32_t (&x)[16], uint32_t (&y)[16], const uint2* tws, int lane) {
+  constexpr uint32_t P = Prime<PR>::P;
+  if constexpr (S < 4) {
+    for8([&](auto kc) {
+      constexpr int r = bfly_reg<RB>(decltype(kc)::value);
+      constexpr TwPair c = twiddle(P, PR ? PSI2 : PSI1, (2u << S) - 1 - (uint32_t)(r >> (4 - S)));
+      const uint32_t u = x[r], v = x[r | (1 << RB)], u2 = y[r], v2 = y[r | (1 << RB)];
+      x[r] = inv_reduces(S) ? reduce_s(u + v, P) : u + v;
+      x[r | (1 << RB)] = shoup_c<c.w, c.q, P>(v - u);
+      y[r] = inv_reduces(S) ? reduce_s(u2 + v2, P) : u2 + v2;
+      y[r | (1 << RB)] = shoup_c<c.w, c.q, P>(v2 - u2);
+    });
+  } else {
+    uint2 w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      w[k] = tws[(1 << S) + tw_perm(S, (1 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S)))];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = bfly_reg<RB>(k);
+      bfly_gs_neg<inv_bound(S), inv_reduces(S)>(x[r], x[r | (1 << RB)], w[k].x, w[k].y, P);
+      bfly_gs_neg<inv_bound(S), inv_reduces(S)>(y[r], y[r | (1 << RB)], w[k].x, w[k].y, P);
+    }
+  }
+}
+
+__device__ __forceinline__ void transpose_y_to_a_pair(uint32_t (&x)[16], uint32_t (&y)[16], uint32_t* bufx,
+                                                      uint32_t* bufy, int lane) {
+  wave_lds_sync();  // earlier readers of the buffers are done
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    bufx[lds_slot1(lay_y(lane, r))] = x[r];
+    bufy[lds_slot1(lay_y(lane, r))] = y[r];
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint2 t = *reinterpret_cast<const uint2*>(bufx + lds_slot1(lay_a(lane, 2 * k)));
+    const uint2 u = *reinterpret_cast<const uint2*>(bufy + lds_slot1(lay_a(lane, 2 * k)));
+    x[2 * k] = t.x;
+    x[2 * k + 1] = t.y;
+    y[2 * k] = u.x;
+    y[2 * k + 1] = u.y;
+  }
+}
+
+template <int PR>
+__device__ __forceinline__ void ntt_inv1_pair(uint32_t (&x)[16], uint32_t (&y)[16], uint32_t* bufx, uint32_t* bufy,
+                                              const uint2* tws, int lane) {
+  inv_stage1_pair<PR, 9, lay_z, 2>(x, y, tws, lane);
+  inv_stage1_pair<PR, 8, lay_z, 3>(x, y, tws, lane);
+  swap_yz(x);  // layout Z -> Y
+  swap_yz(y);
+  inv_stage1_pair<PR, 7, lay_y, 0>(x, y, tws, lane);
+  inv_stage1_pair<PR, 6, lay_y, 1>(x, y, tws, lane);
+  inv_stage1_pair<PR, 5, lay_y, 2>(x, y, tws, lane);
+  inv_stage1_pair<PR, 4, lay_y, 3>(x, y, tws, lane);
+  transpose_y_to_a_pair(x, y, bufx, bufy, lane);
+  inv_stage1_pair<PR, 3, lay_a, 0>(x, y, tws, lane);
+  inv_stage1_pair<PR, 2, lay_a, 1>(x, y, tws, lane);
+  inv_stage1_pair<PR, 1, lay_a, 2>(x, y, tws, lane);
+  inv_stage1_pair<PR, 0, lay_a, 3>(x, y, tws, lane);
+}
+
 }  // namespace vlp
