@@ -318,7 +318,7 @@ __device__ __forceinline__ void br2_rotate(const BrItem& I, uint32_t* acc, const
       keep[r] = redc_s(KEEP ? m1[r] : m0[r], P, PINV);
       x[r] = redc_s(KEEP ? m0[r] : m1[r], P, PINV);
     }
-    ntt_inv1_pair<PR>(keep, x, buf, buf2, tws, lane);  // keep ends in (-P/2, 3P/2): the lift takes lazy residues
+    ntt_inv1_pair<PR>(keep, x, buf, buf2, tws, lane);  // both end below 16P: the lift takes lazy residues
     wave_lds_sync();  // the transform's last reads of buf are done
 #pragma unroll
     for (int r = 0; r < 16; ++r) buf[r * 64 + lane] = x[r];
@@ -495,7 +495,7 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
     wave_lds_sync();  // the transform's last reads of buf are done
     constexpr int MINE = PR * 8, THEIRS = 8 - PR * 8;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) buf[(THEIRS + r) * 64 + lane] = x[THEIRS + r];  // lazy: the lift takes (-P/2, 3P/2)
+    for (int r = 0; r < 8; ++r) buf[(THEIRS + r) * 64 + lane] = x[THEIRS + r];  // lazy: the lift takes |x| < 16P
     __syncthreads();  // B2
     uint32_t* poly = acc + H * RING_N;
     uint32_t old[8], o2[8];

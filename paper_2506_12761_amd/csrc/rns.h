@@ -19,10 +19,10 @@
 //   - six products of such values and canonical key residues stay far
 //     inside the int64 range, and one Montgomery reduction of their sum
 //     lands within (-4P, 4P);
-//   - the inverse transform reduces only at three of its ten stages: a
+//   - the inverse transform reduces only at two of its ten stages: a
 //     Gentleman-Sande sum doubles the bound, and inputs below 4P may double
 //     three times (32P < 2^31) before a Shoup product by 1 brings them back
-//     into (-P/2, 3P/2).
+//     into (-P/2, 3P/2); its outputs, below 16P, go to the lift unreduced.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -165,14 +165,14 @@ constexpr int64_t C12S = C12 > P2 / 2 ? (int64_t)C12 - P2 : (int64_t)C12;
 constexpr int64_t C12S_Q = (C12S * ((int64_t)1 << 32) - ((C12S * ((int64_t)1 << 32)) % P2 + P2) % P2) / P2;
 
 // Low 32 bits of the centred lift of (x1 mod P1, x2 mod P2) for signed
-// residues x1 in (-P1, 2 P1) and x2 in (-P2, 2 P2).  With
+// residues |x1| < 16 P1 and |x2| < 16 P2 (so |x2 - x1| < 32 P1 < 2^31).  With
 // h = (x2 - x1) P1^-1 mod P2 taken in (-P2/2, 3 P2/2) (one signed Shoup
 // product), the integer X (|X| < 6 * 1024 * 64 * 2^32 < 0.37513 Q) is
-// x1 + P1 h, or that minus Q: in the first case h < 0.37513 P2 + 1, in the
-// second h > 0.62487 P2 - 2, so h > P2/2 tells them apart and only the low
+// x1 + P1 h, or that minus Q: in the first case h < 0.37513 P2 + 16, in the
+// second h > 0.62487 P2 - 16, so h > P2/2 tells them apart and only the low
 // words are needed.
 static_assert((6.0 * 1024 * 64 * 4294967296.0) / ((double)P1 * (double)P2) < 0.37513 &&
-                  0.37513 * P2 + 1 < P2 / 2 && 0.62487 * P2 - 2 > P2 / 2,
+                  0.37513 * P2 + 16 < P2 / 2 && 0.62487 * P2 - 16 > P2 / 2 && 32ull * P1 < (1ull << 31),
               "CRT lift decision range");
 __device__ __forceinline__ uint32_t crt_lift_s(uint32_t x1, uint32_t x2) {
   const uint32_t h = shoup_s(x2 - x1, (uint32_t)(int32_t)C12S, (uint32_t)(int32_t)C12S_Q, P2);

@@ -14,8 +14,8 @@
 // Butterflies are lazy and work on signed residues (rns.h): the forward
 // transform never reduces (each stage raises the magnitude bound by 3P/2:
 // digits end below 16P); the inverse takes inputs below 4P in magnitude, lets
-// its sums double the bound and reduces them at three of its ten stages
-// (inv_reduces), ending in (-P/2, 3P/2).  Twiddles are signed (|w| < P/2) and
+// its sums double the bound and reduces them at two of its ten stages
+// (inv_reduces), ending below 16P.  Twiddles are signed (|w| < P/2) and
 // carry their Shoup quotient floor(w 2^32 / P).
 //
 // Three register layouts keep every butterfly inside a lane (a = lane & 15,
@@ -101,17 +101,18 @@ __device__ __forceinline__ void bfly_gs_neg(uint32_t& x, uint32_t& y, uint32_t w
 // Bounds of the inverse stages (run from S = 9 down to 0), in multiples of P:
 // the magnitude bound of stage S's inputs and whether it reduces its sums.
 // Inputs start below 4P; a stage's outputs are below twice its input bound,
-// or 2P if it reduces; no sum or difference reaches 32P.
+// or 2P if it reduces; no sum or difference reaches 32P.  The outputs end
+// below 16P, the range the CRT lift takes (rns.h).
 __host__ __device__ constexpr int inv_bound(int S) {
   return S == 9 ? 4 : S == 8 ? 8 : S == 7 ? 16 : S == 6 ? 2 : S == 5 ? 4 : S == 4 ? 8 : S == 3 ? 16 : S == 2 ? 2 : S == 1 ? 4 : 8;
 }
-__host__ __device__ constexpr bool inv_reduces(int S) { return S == 7 || S == 3 || S == 0; }
+__host__ __device__ constexpr bool inv_reduces(int S) { return S == 7 || S == 3; }
 __host__ __device__ constexpr bool inv_bounds_hold() {
   for (int S = 9; S >= 0; --S) {
     if (2 * inv_bound(S) > 32) return false;
     const int out = inv_reduces(S) ? 2 : 2 * inv_bound(S);
     if (S > 0 && inv_bound(S - 1) != out) return false;
-    if (S == 0 && out != 2) return false;
+    if (S == 0 && out > 16) return false;
   }
   return inv_bound(9) == 4;
 }
@@ -212,7 +213,7 @@ __device__ __forceinline__ void ntt_fwd(Poly2& v, uint2* buf, const Tw* tw, cons
   fwd_stage<9, lay_z, 2>(v, tw, lane);
 }
 
-// Inverse without 1/N: layout Z (|values| < 4P) -> layout A (values in (-P/2, 3P/2)).
+// Inverse without 1/N: layout Z (|values| < 4P) -> layout A (|values| < 16P).
 __device__ __forceinline__ void ntt_inv(Poly2& v, uint2* buf, const Tw* tw, const Tw* __restrict__ gtw, int lane) {
   inv_stage<9, lay_z, 2>(v, tw, lane);
   inv_stage<8, lay_z, 3>(v, tw, lane);
