@@ -107,9 +107,11 @@ class GpuExecutor(Executor):
 
     @staticmethod
     def _input_bytes(req: Request) -> int:
+        """Device bytes of a request's buffers: query, database locations and
+        payload, R and v (631-word ciphertexts)."""
         d = req.d if req.mode != "idm" else 1
         loc = req.M * d * (2 if req.mode == "intv" else 1) * req.l_I
-        return 631 * 4 * (d * req.l_I + loc + 2 * req.M * req.l_S + req.l_S + req.M)
+        return 631 * 4 * (d * req.l_I + loc + req.M * req.l_S + req.l_S + req.M)
 
     def held(self) -> int:
         """Device bytes held: the library's (programs, keysets, scratch) and the inputs."""

@@ -196,3 +196,16 @@ def test_srpt_selection_order_and_cap():
     assert [r.handle for r in select_step(reqs, Ex(), "all", 5)] == [1, 2, 3, 4]
     with pytest.raises(ValueError):
         select_step(reqs, Ex(), "fastest", None)
+
+
+def test_input_bytes_of_each_mode():
+    """The executor's estimate of a request's buffers: query, locations,
+    payload, R and v, each 631 words of 4 bytes."""
+    from paper_2506_12761_amd.serve import GpuExecutor
+    ct = 631 * 4
+    r = Request(0, 0, "intv", 10, 16, 64, 2, arrival=0.0)
+    assert GpuExecutor._input_bytes(r) == ct * (2 * 16 + 10 * 2 * 2 * 16 + 10 * 64 + 64 + 10)
+    r = Request(0, 0, "cov", 7, 20, 3, 2, arrival=0.0)
+    assert GpuExecutor._input_bytes(r) == ct * (2 * 20 + 7 * 2 * 20 + 7 * 3 + 3 + 7)
+    r = Request(0, 0, "idm", 5, 32, 0, 1, arrival=0.0)
+    assert GpuExecutor._input_bytes(r) == ct * (32 + 5 * 32 + 0 + 0 + 5)
