@@ -529,6 +529,8 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="device memory the server may hold")
     ap.add_argument("--keyswitch", action="store_true", help="time key switching alone instead")
     ap.add_argument("--ks-gates", type=int, default=16384, help="key switches per call with --keyswitch")
+    ap.add_argument("--graph-steps", type=int, default=3,
+                    help="after the timed steps, time this many HIP-graph replays of the same program (0: none)")
     ap.add_argument("--no-config4", action="store_true",
                     help="skip the 65,536-record identifier-match query reported beside the main line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -642,6 +644,29 @@ def main():
     value = br_step * args.steps / elapsed
     log("timed %d steps in %.3f s: %.1f blind rotations/s" % (args.steps, elapsed, value))
 
+    # The same step replayed as a HIP graph (the program's whole level sequence
+    # captured once; a reset and one graph launch per step), timed beside it.
+    graph_replay = None
+    if len(progs) == 1 and not args.graph and not args.progress and args.graph_steps > 0:
+        vlp.vlp_program_reset(ctx.ctx, progs[0])
+        vlp.vlp_program_run(ctx.ctx, progs[0], use_graph=True)  # captures the graph
+        ctx.sync()
+        evg = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.graph_steps)]
+        tg0 = time.perf_counter()
+        for k in range(args.graph_steps):
+            evg[k][0].record(stream)
+            vlp.vlp_program_reset(ctx.ctx, progs[0])
+            vlp.vlp_program_run(ctx.ctx, progs[0], use_graph=True)
+            evg[k][1].record(stream)
+        ctx.sync()
+        g_elapsed = time.perf_counter() - tg0
+        graph_replay = {"steps": args.graph_steps, "ms_per_step": g_elapsed * 1e3 / args.graph_steps,
+                        "value": br_step * args.graph_steps / g_elapsed,
+                        "device_ms_per_step": [a.elapsed_time(b) for a, b in evg],
+                        "vs_launches": elapsed / args.steps / (g_elapsed / args.graph_steps)}
+        log("graph replay: %.1f ms per step (launches: %.1f)" % (graph_replay["ms_per_step"], elapsed * 1e3 / args.steps))
+
     # Plain form: one AND gate per launch, launched back to back.
     P = args.plain_gates
     a = uniform_words(ctx, (P, 631), 7)
@@ -721,6 +746,7 @@ def main():
         "speedup_batched_vs_plain": value / plain_rate,
         "query_latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
         "roofline": roofline,
+        "graph_replay": graph_replay,
         "cpu_baseline": cpu,
         "config4": config4,
     }
