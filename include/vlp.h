@@ -79,7 +79,13 @@ typedef struct {
 
 /* Query shape (Section 3.2, "Secure Parameter Transmission"): M records,
  * l_I bits per coordinate or identifier, l_S payload bits per record,
- * d coordinates (1 or 2 for IntV and CoV; ignored for IdM).
+ * d coordinates (1 or 2 for IntV and CoV; ignored for IdM). */
+typedef struct {
+    vlp_mode mode;
+    uint32_t M, l_I, l_S, d;
+} vlp_shape;
+
+/* The circuits that evaluate a shape (Section 6.1).
  * optimized = 1 uses the OPT circuits (Alg. 11 comparators, Alg. 12 equality
  * tree, pairwise XOR aggregation); 0 uses Alg. 7's AND chain and Alg. 10's
  * XOR chain from a trivial zero.
@@ -89,13 +95,14 @@ typedef struct {
  * consecutive groups of k, a group of one passed through, repeated on the
  * group results.  Not in the paper; k <= 16 keeps the summed input noise
  * (4k times a gate output's) beyond 8 standard deviations of the 1/4
- * decision distance. */
+ * decision distance.
+ * The calls that take a shape use {optimized = 1, agg_k = 0}; their _ex
+ * forms take the circuits as an extra argument (NULL: that default).
+ * VLP_EINVAL for agg_k = 1 or agg_k > 16. */
 typedef struct {
-    vlp_mode mode;
-    uint32_t M, l_I, l_S, d;
     uint32_t optimized;
     uint32_t agg_k;
-} vlp_shape;
+} vlp_circuit;
 
 typedef struct vlp_ctx vlp_ctx;
 typedef struct vlp_keyset vlp_keyset;
@@ -183,6 +190,9 @@ vlp_status vlp_gate_noalloc(vlp_ctx *ctx, const vlp_keyset *ks, vlp_gate_op op, 
  * it; intermediate ciphertexts are held within the context budget. */
 vlp_status vlp_evaluate(vlp_ctx *ctx, const vlp_keyset *ks, const vlp_shape *shape, const uint32_t *query_dev,
                         const uint32_t *db_loc_dev, const uint32_t *db_pay_dev, uint32_t *R_dev, uint32_t *v_out_dev);
+vlp_status vlp_evaluate_ex(vlp_ctx *ctx, const vlp_keyset *ks, const vlp_shape *shape, const vlp_circuit *circuit,
+                           const uint32_t *query_dev, const uint32_t *db_loc_dev, const uint32_t *db_pay_dev,
+                           uint32_t *R_dev, uint32_t *v_out_dev);
 
 /* ServerEnc (Alg. 2): the server encrypts its plaintext database under the
  * client's public key (Alg. 1: one encryption of zero per database bit), so
@@ -220,6 +230,9 @@ vlp_status vlp_server_encrypt(vlp_ctx *ctx, const vlp_shape *shape, const uint32
 vlp_status vlp_program_create(vlp_ctx *ctx, const vlp_keyset *ks, const vlp_shape *shape, const uint32_t *query_dev,
                               const uint32_t *db_loc_dev, const uint32_t *db_pay_dev, uint32_t *R_dev,
                               uint32_t *v_out_dev, vlp_program **out);
+vlp_status vlp_program_create_ex(vlp_ctx *ctx, const vlp_keyset *ks, const vlp_shape *shape,
+                                 const vlp_circuit *circuit, const uint32_t *query_dev, const uint32_t *db_loc_dev,
+                                 const uint32_t *db_pay_dev, uint32_t *R_dev, uint32_t *v_out_dev, vlp_program **out);
 vlp_status vlp_program_reset(vlp_program *prog);
 vlp_status vlp_step(vlp_ctx *ctx, vlp_program *const *progs, size_t n_progs, size_t *remaining);
 vlp_status vlp_program_run(vlp_ctx *ctx, vlp_program *prog, int use_graph);
@@ -227,6 +240,8 @@ vlp_status vlp_program_run(vlp_ctx *ctx, vlp_program *prog, int use_graph);
 /* The same counts for a shape, computed on the host without a device. */
 vlp_status vlp_plan_counts(const vlp_shape *shape, uint64_t *gates, uint64_t *blind_rotations, uint64_t *key_switches,
                            uint32_t *levels);
+vlp_status vlp_plan_counts_ex(const vlp_shape *shape, const vlp_circuit *circuit, uint64_t *gates,
+                              uint64_t *blind_rotations, uint64_t *key_switches, uint32_t *levels);
 /* Device bytes vlp_program_create would reserve against the budget for a
  * shape (with or without a v_out buffer), computed on the host: work items,
  * intermediate ciphertexts, key-switching digits and the program's share of
@@ -234,6 +249,7 @@ vlp_status vlp_plan_counts(const vlp_shape *shape, uint64_t *gates, uint64_t *bl
  * only when these bytes (plus its input buffers) fit.  VLP_EINVAL for a bad
  * shape or a NULL argument. */
 vlp_status vlp_plan_bytes(const vlp_shape *shape, int with_v_out, size_t *bytes);
+vlp_status vlp_plan_bytes_ex(const vlp_shape *shape, const vlp_circuit *circuit, int with_v_out, size_t *bytes);
 /* Blind rotations and key switches of one level (0-based) of a program;
  * VLP_EINVAL past the last level. */
 vlp_status vlp_program_level_counts(const vlp_program *prog, uint32_t level, uint64_t *blind_rotations,

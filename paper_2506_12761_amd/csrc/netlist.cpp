@@ -168,19 +168,23 @@ bool shape_valid(const vlp_shape& sh, const char** why) {
   if (sh.mode == VLP_INTV && l < 2) { *why = "IntV needs l_I >= 2"; return false; }
   if (lS > 1024) { *why = "l_S must be <= 1024"; return false; }
   if (sh.mode != VLP_IDM && (d < 1 || d > 2)) { *why = "d must be 1 or 2"; return false; }
-  if (sh.agg_k == 1 || sh.agg_k > AGG_K_MAX) { *why = "agg_k must be 0 or in [2, 16]"; return false; }
   return true;
 }
 
-bool build_netlist(const vlp_shape& sh, Netlist& nl, const char** why) {
+bool circuit_valid(const vlp_circuit& c, const char** why) {
+  if (c.agg_k == 1 || c.agg_k > AGG_K_MAX) { *why = "agg_k must be 0 or in [2, 16]"; return false; }
+  return true;
+}
+
+bool build_netlist(const vlp_shape& sh, const vlp_circuit& circ, Netlist& nl, const char** why) {
   nl = Netlist();
-  if (!shape_valid(sh, why)) return false;
+  if (!shape_valid(sh, why) || !circuit_valid(circ, why)) return false;
   const uint32_t M = sh.M, l = sh.l_I, lS = sh.l_S;
   const uint32_t d = sh.mode == VLP_IDM ? 1 : sh.d;
   nl.M = M;
   nl.l_S = lS;
   Builder B{nl};
-  const bool opt = sh.optimized != 0;
+  const bool opt = circ.optimized != 0;
 
   // Validation (Alg. 4 / Alg. 8 / IdM), record by record.
   nl.v_of_record.resize(M);
@@ -216,9 +220,9 @@ bool build_netlist(const vlp_shape& sh, Netlist& nl, const char** why) {
   std::vector<std::vector<Operand>> S(M, std::vector<Operand>(lS));
   for (uint32_t i = 0; i < M; ++i)
     for (uint32_t j = 0; j < lS; ++j) S[i][j] = B.AND(nl.v_of_record[i], Operand::pay(i * lS + j));
-  if (sh.agg_k >= 2) {
+  if (circ.agg_k >= 2) {
     // Consecutive groups of k (a group of one passes through), repeated on the group results.
-    const uint32_t K = sh.agg_k;
+    const uint32_t K = circ.agg_k;
     std::vector<std::vector<Operand>> cur = S;
     while (cur.size() > 1) {
       std::vector<std::vector<Operand>> nxt;

@@ -47,13 +47,16 @@ struct Netlist {
   uint64_t key_switches() const;
 };
 
-// Builds the gate netlist of Algorithm 3 for `shape` (validation by IntV,
-// CoV or IdM, zero-out, aggregation).  Returns false for shapes out of range.
+// Builds the gate netlist of Algorithm 3 for `shape` with the circuits
+// `circuit` (validation by IntV, CoV or IdM, zero-out, aggregation).  Returns
+// false for shapes or circuits out of range.
 // Limits every call taking a shape enforces (mode, M, l_I, l_S, d).
 bool shape_valid(const vlp_shape& shape, const char** why);
+// agg_k is 0 or in [2, 16].
+bool circuit_valid(const vlp_circuit& circuit, const char** why);
 // Appends one gate as the circuit builders do (a gate of trivial operands
 // only becomes the trivial operand of its value) and returns its operand.
 Operand add_gate(Netlist& nl, uint8_t op, Operand a, Operand b, Operand c = Operand());
-bool build_netlist(const vlp_shape& shape, Netlist& out, const char** why);
+bool build_netlist(const vlp_shape& shape, const vlp_circuit& circuit, Netlist& out, const char** why);
 
 }  // namespace vlp

@@ -61,6 +61,7 @@ struct vlp_program {
   vlp_ctx* ctx;
   vlp_keyset* ks;
   vlp_shape shape;
+  vlp_circuit circuit;
   uint64_t gates = 0, brs = 0, kss = 0;
   std::vector<Level> levels;
   uint32_t next_level = 0;
@@ -691,11 +692,20 @@ static const char* program_sizes(const Netlist& nl, bool with_v_out, ProgramSize
   return nullptr;
 }
 
+// The circuits of the calls without a circuit argument (and of a NULL one).
+static const vlp_circuit DEFAULT_CIRCUIT = {1, 0};
+static const vlp_circuit& circuit_or_default(const vlp_circuit* c) { return c ? *c : DEFAULT_CIRCUIT; }
+
 extern "C" vlp_status vlp_plan_bytes(const vlp_shape* shape, int with_v_out, size_t* bytes) {
+  return vlp_plan_bytes_ex(shape, nullptr, with_v_out, bytes);
+}
+
+extern "C" vlp_status vlp_plan_bytes_ex(const vlp_shape* shape, const vlp_circuit* circuit, int with_v_out,
+                                        size_t* bytes) {
   if (!shape || !bytes) return VLP_EINVAL;
   Netlist nl;
   const char* why = "";
-  if (!build_netlist(*shape, nl, &why)) return VLP_EINVAL;
+  if (!build_netlist(*shape, circuit_or_default(circuit), nl, &why)) return VLP_EINVAL;
   ProgramSizes z;
   if (program_sizes(nl, with_v_out != 0, z)) return VLP_EINVAL;
   *bytes = z.total + z.step;
@@ -704,10 +714,15 @@ extern "C" vlp_status vlp_plan_bytes(const vlp_shape* shape, int with_v_out, siz
 
 extern "C" vlp_status vlp_plan_counts(const vlp_shape* shape, uint64_t* gates, uint64_t* brs, uint64_t* kss,
                                       uint32_t* levels) {
+  return vlp_plan_counts_ex(shape, nullptr, gates, brs, kss, levels);
+}
+
+extern "C" vlp_status vlp_plan_counts_ex(const vlp_shape* shape, const vlp_circuit* circuit, uint64_t* gates,
+                                         uint64_t* brs, uint64_t* kss, uint32_t* levels) {
   if (!shape) return VLP_EINVAL;
   Netlist nl;
   const char* why = "";
-  if (!build_netlist(*shape, nl, &why)) return VLP_EINVAL;
+  if (!build_netlist(*shape, circuit_or_default(circuit), nl, &why)) return VLP_EINVAL;
   if (gates) *gates = nl.gates.size();
   if (brs) *brs = nl.blind_rotations();
   if (kss) *kss = nl.key_switches();
@@ -719,7 +734,15 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
                                          const uint32_t* query_dev, const uint32_t* db_loc_dev,
                                          const uint32_t* db_pay_dev, uint32_t* R_dev, uint32_t* v_out_dev,
                                          vlp_program** out) {
+  return vlp_program_create_ex(ctx, ks_c, shape, nullptr, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev, out);
+}
+
+extern "C" vlp_status vlp_program_create_ex(vlp_ctx* ctx, const vlp_keyset* ks_c, const vlp_shape* shape,
+                                            const vlp_circuit* circuit_arg, const uint32_t* query_dev,
+                                            const uint32_t* db_loc_dev, const uint32_t* db_pay_dev, uint32_t* R_dev,
+                                            uint32_t* v_out_dev, vlp_program** out) {
   if (!ctx) return VLP_EINVAL;
+  const vlp_circuit& circuit = circuit_or_default(circuit_arg);
   vlp_keyset* ks = const_cast<vlp_keyset*>(ks_c);
   if (!ks || ks->ctx != ctx || !shape || !out || !query_dev || !db_loc_dev)
     return fail(ctx, VLP_EINVAL, "null or foreign argument");
@@ -727,7 +750,7 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   if (shape->l_S > 0 && (!db_pay_dev || !R_dev)) return fail(ctx, VLP_EINVAL, "l_S > 0 needs db_pay and R");
   Netlist nl;
   const char* why = "";
-  if (!build_netlist(*shape, nl, &why)) return fail(ctx, VLP_EINVAL, "bad shape: %s", why);
+  if (!build_netlist(*shape, circuit, nl, &why)) return fail(ctx, VLP_EINVAL, "bad shape: %s", why);
   size_t wq, wl, wp;
   shape_words(shape, &wq, &wl, &wp);
   const size_t M = nl.M, lS = nl.l_S;
@@ -767,6 +790,7 @@ extern "C" vlp_status vlp_program_create(vlp_ctx* ctx, const vlp_keyset* ks_c, c
   prog->ctx = ctx;
   prog->ks = ks;
   prog->shape = *shape;
+  prog->circuit = circuit;
   prog->gates = nl.gates.size();
   prog->brs = n_br;
   prog->kss = n_ks;
@@ -1079,12 +1103,21 @@ extern "C" vlp_status vlp_program_run(vlp_ctx* ctx, vlp_program* prog, int use_g
 extern "C" vlp_status vlp_evaluate(vlp_ctx* ctx, const vlp_keyset* ks, const vlp_shape* shape,
                                    const uint32_t* query_dev, const uint32_t* db_loc_dev, const uint32_t* db_pay_dev,
                                    uint32_t* R_dev, uint32_t* v_out_dev) {
+  return vlp_evaluate_ex(ctx, ks, shape, nullptr, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev);
+}
+
+extern "C" vlp_status vlp_evaluate_ex(vlp_ctx* ctx, const vlp_keyset* ks, const vlp_shape* shape,
+                                      const vlp_circuit* circuit_arg, const uint32_t* query_dev,
+                                      const uint32_t* db_loc_dev, const uint32_t* db_pay_dev, uint32_t* R_dev,
+                                      uint32_t* v_out_dev) {
   if (!ctx) return VLP_EINVAL;
   if (!shape) return fail(ctx, VLP_EINVAL, "shape is NULL");
+  const vlp_circuit& circuit = circuit_or_default(circuit_arg);
   vlp_program* prog = nullptr;
   for (auto it = ctx->eval_cache.begin(); it != ctx->eval_cache.end(); ++it) {
     vlp_program* p = *it;
-    if (p->ks == ks && memcmp(&p->shape, shape, sizeof(vlp_shape)) == 0 && p->q == query_dev &&
+    if (p->ks == ks && memcmp(&p->shape, shape, sizeof(vlp_shape)) == 0 &&
+        p->circuit.optimized == circuit.optimized && p->circuit.agg_k == circuit.agg_k && p->q == query_dev &&
         p->loc == db_loc_dev && p->pay == db_pay_dev && p->R == R_dev && p->v == v_out_dev) {
       prog = p;
       ctx->eval_cache.erase(it);
@@ -1092,13 +1125,14 @@ extern "C" vlp_status vlp_evaluate(vlp_ctx* ctx, const vlp_keyset* ks, const vlp
     }
   }
   if (!prog) {
-    vlp_status st = vlp_program_create(ctx, ks, shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev, &prog);
+    vlp_status st =
+        vlp_program_create_ex(ctx, ks, shape, &circuit, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev, &prog);
     if (st == VLP_EBUDGET && !ctx->eval_cache.empty()) {
       // Make room by dropping cached programs, then retry once.
       (void)hipStreamSynchronize(ctx->stream);
       for (vlp_program* p : ctx->eval_cache) program_free(p);
       ctx->eval_cache.clear();
-      st = vlp_program_create(ctx, ks, shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev, &prog);
+      st = vlp_program_create_ex(ctx, ks, shape, &circuit, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev, &prog);
     }
     if (st != VLP_OK) return st;
   }

@@ -30,9 +30,10 @@ MU = 1 << 29
 EXPORTS = [
     "vlp_version", "vlp_default_params", "vlp_ctx_create", "vlp_ctx_destroy", "vlp_last_error", "vlp_mem_info",
     "vlp_keyset_load", "vlp_keyset_destroy", "vlp_bootstrap", "vlp_keyswitch", "vlp_gate", "vlp_gate_noalloc",
-    "vlp_evaluate", "vlp_server_encrypt",
-    "vlp_program_create", "vlp_program_reset", "vlp_step", "vlp_program_run", "vlp_program_counts",
-    "vlp_plan_counts", "vlp_plan_bytes", "vlp_program_level_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
+    "vlp_evaluate", "vlp_evaluate_ex", "vlp_server_encrypt",
+    "vlp_program_create", "vlp_program_create_ex", "vlp_program_reset", "vlp_step", "vlp_program_run",
+    "vlp_program_counts", "vlp_plan_counts", "vlp_plan_counts_ex", "vlp_plan_bytes", "vlp_plan_bytes_ex",
+    "vlp_program_level_counts", "vlp_program_destroy", "vlp_get_tuning", "vlp_set_tuning", "vlp_sync",
     "vlp_profile_enable", "vlp_profile_read", "vlp_measure_modmul_peak",
 ]
 
@@ -49,8 +50,17 @@ class vlp_params(ctypes.Structure):
 
 class vlp_shape(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("M", ctypes.c_uint32), ("l_I", ctypes.c_uint32),
-                ("l_S", ctypes.c_uint32), ("d", ctypes.c_uint32), ("optimized", ctypes.c_uint32),
-                ("agg_k", ctypes.c_uint32)]
+                ("l_S", ctypes.c_uint32), ("d", ctypes.c_uint32)]
+
+
+class vlp_circuit(ctypes.Structure):
+    _fields_ = [("optimized", ctypes.c_uint32), ("agg_k", ctypes.c_uint32)]
+
+
+class Query(ctypes.Structure):
+    """A shape with the circuits that evaluate it (make_shape's result); the
+    wrappers below pass it to the _ex entry points."""
+    _fields_ = [("shape", vlp_shape), ("circuit", vlp_circuit)]
 
 
 class vlp_kernel_stats(ctypes.Structure):
@@ -88,14 +98,19 @@ def lib():
             "vlp_gate": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp, vp, vp, sz]),
             "vlp_gate_noalloc": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp, vp, vp, sz]),
             "vlp_evaluate": (ctypes.c_int, [vp, vp, P(vlp_shape), vp, vp, vp, vp, vp]),
+            "vlp_evaluate_ex": (ctypes.c_int, [vp, vp, P(vlp_shape), P(vlp_circuit), vp, vp, vp, vp, vp]),
             "vlp_server_encrypt": (ctypes.c_int, [vp, P(vlp_shape), vp, vp, vp, vp, vp, vp]),
             "vlp_program_create": (ctypes.c_int, [vp, vp, P(vlp_shape), vp, vp, vp, vp, vp, P(vp)]),
+            "vlp_program_create_ex": (ctypes.c_int, [vp, vp, P(vlp_shape), P(vlp_circuit), vp, vp, vp, vp, vp,
+                                                     P(vp)]),
             "vlp_program_reset": (ctypes.c_int, [vp]),
             "vlp_step": (ctypes.c_int, [vp, P(vp), sz, P(sz)]),
             "vlp_program_run": (ctypes.c_int, [vp, vp, ctypes.c_int]),
             "vlp_program_counts": (ctypes.c_int, [vp, P(u64), P(u64), P(u64), P(u32)]),
             "vlp_plan_counts": (ctypes.c_int, [P(vlp_shape), P(u64), P(u64), P(u64), P(u32)]),
+            "vlp_plan_counts_ex": (ctypes.c_int, [P(vlp_shape), P(vlp_circuit), P(u64), P(u64), P(u64), P(u32)]),
             "vlp_plan_bytes": (ctypes.c_int, [P(vlp_shape), ctypes.c_int, P(sz)]),
+            "vlp_plan_bytes_ex": (ctypes.c_int, [P(vlp_shape), P(vlp_circuit), ctypes.c_int, P(sz)]),
             "vlp_program_level_counts": (ctypes.c_int, [vp, u32, P(u64), P(u64)]),
             "vlp_program_destroy": (ctypes.c_int, [vp]),
             "vlp_get_tuning": (ctypes.c_int, [vp, P(vlp_tuning)]),
@@ -198,27 +213,56 @@ def vlp_gate_noalloc(ctx, ks, op, a_dev, b_dev, c_dev, out_dev, B: int) -> None:
     _check(ctx, lib().vlp_gate_noalloc(ctx, ks, op, _ptr(a_dev), _ptr(b_dev), _ptr(c_dev), _ptr(out_dev), B))
 
 
-def make_shape(mode, M, l_I, l_S=0, d=2, optimized=True, agg_k=0) -> vlp_shape:
+def make_shape(mode, M, l_I, l_S=0, d=2, optimized=True, agg_k=0) -> Query:
     if isinstance(mode, str):
         mode = MODES[mode]
-    return vlp_shape(mode, M, l_I, l_S, d, 1 if optimized else 0, agg_k)
+    return Query(vlp_shape(mode, M, l_I, l_S, d), vlp_circuit(1 if optimized else 0, agg_k))
 
 
-def vlp_evaluate(ctx, ks, shape: vlp_shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev) -> None:
-    _check(ctx, lib().vlp_evaluate(ctx, ks, ctypes.byref(shape), _ptr(query_dev), _ptr(db_loc_dev),
+def _split(shape):
+    """(vlp_shape, vlp_circuit or None) of a vlp_shape or a Query."""
+    if isinstance(shape, Query):
+        return shape.shape, shape.circuit
+    return shape, None
+
+
+def vlp_evaluate(ctx, ks, shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev) -> None:
+    s, c = _split(shape)
+    if c is not None:
+        return vlp_evaluate_ex(ctx, ks, s, c, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev)
+    _check(ctx, lib().vlp_evaluate(ctx, ks, ctypes.byref(s), _ptr(query_dev), _ptr(db_loc_dev),
                                    _ptr(db_pay_dev), _ptr(R_dev), _ptr(v_out_dev)))
 
 
-def vlp_server_encrypt(ctx, shape: vlp_shape, pk_loc_dev, pk_pay_dev, loc_dev, pay_dev, out_loc_dev,
-                       out_pay_dev) -> None:
-    _check(ctx, lib().vlp_server_encrypt(ctx, ctypes.byref(shape), _ptr(pk_loc_dev), _ptr(pk_pay_dev), _ptr(loc_dev),
+def vlp_evaluate_ex(ctx, ks, shape: vlp_shape, circuit: vlp_circuit | None, query_dev, db_loc_dev, db_pay_dev,
+                    R_dev, v_out_dev) -> None:
+    _check(ctx, lib().vlp_evaluate_ex(ctx, ks, ctypes.byref(shape), ctypes.byref(circuit) if circuit else None,
+                                      _ptr(query_dev), _ptr(db_loc_dev), _ptr(db_pay_dev), _ptr(R_dev),
+                                      _ptr(v_out_dev)))
+
+
+def vlp_server_encrypt(ctx, shape, pk_loc_dev, pk_pay_dev, loc_dev, pay_dev, out_loc_dev, out_pay_dev) -> None:
+    s = _split(shape)[0]
+    _check(ctx, lib().vlp_server_encrypt(ctx, ctypes.byref(s), _ptr(pk_loc_dev), _ptr(pk_pay_dev), _ptr(loc_dev),
                                          _ptr(pay_dev), _ptr(out_loc_dev), _ptr(out_pay_dev)))
 
 
-def vlp_program_create(ctx, ks, shape: vlp_shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev):
+def vlp_program_create(ctx, ks, shape, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev):
+    s, c = _split(shape)
+    if c is not None:
+        return vlp_program_create_ex(ctx, ks, s, c, query_dev, db_loc_dev, db_pay_dev, R_dev, v_out_dev)
     out = ctypes.c_void_p()
-    _check(ctx, lib().vlp_program_create(ctx, ks, ctypes.byref(shape), _ptr(query_dev), _ptr(db_loc_dev),
+    _check(ctx, lib().vlp_program_create(ctx, ks, ctypes.byref(s), _ptr(query_dev), _ptr(db_loc_dev),
                                          _ptr(db_pay_dev), _ptr(R_dev), _ptr(v_out_dev), ctypes.byref(out)))
+    return out.value
+
+
+def vlp_program_create_ex(ctx, ks, shape: vlp_shape, circuit: vlp_circuit | None, query_dev, db_loc_dev,
+                          db_pay_dev, R_dev, v_out_dev):
+    out = ctypes.c_void_p()
+    _check(ctx, lib().vlp_program_create_ex(ctx, ks, ctypes.byref(shape), ctypes.byref(circuit) if circuit else None,
+                                            _ptr(query_dev), _ptr(db_loc_dev), _ptr(db_pay_dev), _ptr(R_dev),
+                                            _ptr(v_out_dev), ctypes.byref(out)))
     return out.value
 
 
@@ -243,19 +287,43 @@ def vlp_program_counts(ctx, prog) -> dict:
     return {"gates": g.value, "blind_rotations": b.value, "key_switches": k.value, "levels": l.value}
 
 
-def vlp_plan_counts(shape: vlp_shape) -> dict:
+def vlp_plan_counts(shape) -> dict:
+    s, c = _split(shape)
+    if c is not None:
+        return vlp_plan_counts_ex(s, c)
     g, b, k, l = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
-    st = lib().vlp_plan_counts(ctypes.byref(shape), ctypes.byref(g), ctypes.byref(b), ctypes.byref(k), ctypes.byref(l))
+    st = lib().vlp_plan_counts(ctypes.byref(s), ctypes.byref(g), ctypes.byref(b), ctypes.byref(k), ctypes.byref(l))
     if st != VLP_OK:
         raise VlpError(st, "bad shape")
     return {"gates": g.value, "blind_rotations": b.value, "key_switches": k.value, "levels": l.value}
 
 
-def vlp_plan_bytes(shape: vlp_shape, with_v_out: bool = True) -> int:
+def vlp_plan_counts_ex(shape: vlp_shape, circuit: vlp_circuit | None) -> dict:
+    g, b, k, l = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
+    st = lib().vlp_plan_counts_ex(ctypes.byref(shape), ctypes.byref(circuit) if circuit else None, ctypes.byref(g),
+                                  ctypes.byref(b), ctypes.byref(k), ctypes.byref(l))
+    if st != VLP_OK:
+        raise VlpError(st, "bad shape or circuit")
+    return {"gates": g.value, "blind_rotations": b.value, "key_switches": k.value, "levels": l.value}
+
+
+def vlp_plan_bytes(shape, with_v_out: bool = True) -> int:
+    s, c = _split(shape)
+    if c is not None:
+        return vlp_plan_bytes_ex(s, c, with_v_out)
     b = ctypes.c_size_t()
-    st = lib().vlp_plan_bytes(ctypes.byref(shape), 1 if with_v_out else 0, ctypes.byref(b))
+    st = lib().vlp_plan_bytes(ctypes.byref(s), 1 if with_v_out else 0, ctypes.byref(b))
     if st != VLP_OK:
         raise VlpError(st, "bad shape")
+    return b.value
+
+
+def vlp_plan_bytes_ex(shape: vlp_shape, circuit: vlp_circuit | None, with_v_out: bool = True) -> int:
+    b = ctypes.c_size_t()
+    st = lib().vlp_plan_bytes_ex(ctypes.byref(shape), ctypes.byref(circuit) if circuit else None,
+                                 1 if with_v_out else 0, ctypes.byref(b))
+    if st != VLP_OK:
+        raise VlpError(st, "bad shape or circuit")
     return b.value
 
 

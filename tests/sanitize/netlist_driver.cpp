@@ -10,10 +10,10 @@
 
 using namespace vlp;
 
-static bool check(const vlp_shape& sh) {
+static bool check(const vlp_shape& sh, const vlp_circuit& circ) {
   Netlist nl;
   const char* why = "";
-  if (!build_netlist(sh, nl, &why)) {
+  if (!build_netlist(sh, circ, nl, &why)) {
     std::printf("rejected a valid shape: %s\n", why);
     return false;
   }
@@ -69,20 +69,24 @@ int main() {
         for (uint32_t lS : {0u, 1u, 4u})
           for (uint32_t opt = 0; opt < 2; ++opt)
             for (uint32_t k : {0u, 2u, 3u, 16u}) {
-              const vlp_shape sh{(vlp_mode)mode, M, l, lS, 2, opt, k};
-              if (!check(sh)) return 1;
+              const vlp_shape sh{(vlp_mode)mode, M, l, lS, 2};
+              if (!check(sh, vlp_circuit{opt, k})) return 1;
               ++n;
             }
-  const vlp_shape big{VLP_IDM, 4, 8, 1024, 1, 1, 16};
-  if (!check(big)) return 1;
+  const vlp_shape big{VLP_IDM, 4, 8, 1024, 1};
+  if (!check(big, vlp_circuit{1, 16})) return 1;
   const char* why = "";
   Netlist nl;
-  for (const vlp_shape& bad : {vlp_shape{VLP_INTV, 3, 1, 0, 1, 1, 0}, vlp_shape{VLP_IDM, 0, 8, 0, 1, 1, 0},
-                               vlp_shape{VLP_COV, 3, 65, 0, 1, 1, 0}, vlp_shape{VLP_COV, 3, 8, 0, 3, 1, 0},
-                               vlp_shape{VLP_IDM, 3, 8, 1025, 1, 1, 0}, vlp_shape{VLP_IDM, 3, 8, 2, 1, 1, 17},
-                               vlp_shape{(vlp_mode)7, 3, 8, 2, 1, 1, 0}})
-    if (build_netlist(bad, nl, &why)) {
+  for (const vlp_shape& bad : {vlp_shape{VLP_INTV, 3, 1, 0, 1}, vlp_shape{VLP_IDM, 0, 8, 0, 1},
+                               vlp_shape{VLP_COV, 3, 65, 0, 1}, vlp_shape{VLP_COV, 3, 8, 0, 3},
+                               vlp_shape{VLP_IDM, 3, 8, 1025, 1}, vlp_shape{(vlp_mode)7, 3, 8, 2, 1}})
+    if (build_netlist(bad, vlp_circuit{1, 0}, nl, &why)) {
       std::printf("accepted an invalid shape\n");
+      return 1;
+    }
+  for (const vlp_circuit& bad : {vlp_circuit{1, 1}, vlp_circuit{1, 17}, vlp_circuit{0, 1u << 31}})
+    if (build_netlist(vlp_shape{VLP_IDM, 3, 8, 2, 1}, bad, nl, &why)) {
+      std::printf("accepted an invalid circuit\n");
       return 1;
     }
   // A MUX with a trivial select is bootstrapped like any other gate (its two

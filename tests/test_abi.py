@@ -113,3 +113,56 @@ def test_measure_peak_rejects_null_outputs():
     L = vlp.lib()
     d = ctypes.c_double()
     assert L.vlp_measure_modmul_peak(0, None, ctypes.byref(d), ctypes.byref(d)) == vlp.VLP_EINVAL
+
+
+SHAPE_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "vlp.h"
+_Static_assert(sizeof(vlp_shape) == 5 * sizeof(uint32_t), "vlp_shape: mode, M, l_I, l_S, d");
+_Static_assert(offsetof(vlp_shape, l_S) == 12 && offsetof(vlp_shape, d) == 16, "field order");
+int main(void) {
+  const vlp_shape sh = {VLP_IDM, 9, 16, 9, 1};
+  const vlp_circuit opt = {1, 0}, base = {0, 0}, bad = {1, 1};
+  uint64_t g[3], b[3], k[3];
+  uint32_t l[3];
+  size_t bytes[2];
+  if (vlp_plan_counts(&sh, &g[0], &b[0], &k[0], &l[0]) != VLP_OK) return 2;
+  if (vlp_plan_counts_ex(&sh, &opt, &g[1], &b[1], &k[1], &l[1]) != VLP_OK) return 3;
+  if (vlp_plan_counts_ex(&sh, &base, &g[2], &b[2], &k[2], &l[2]) != VLP_OK) return 4;
+  if (vlp_plan_counts_ex(&sh, &bad, &g[2], &b[2], &k[2], &l[2]) != VLP_EINVAL) return 5;
+  if (vlp_plan_bytes(&sh, 1, &bytes[0]) != VLP_OK || vlp_plan_bytes_ex(&sh, NULL, 1, &bytes[1]) != VLP_OK) return 6;
+  if (vlp_plan_counts_ex(&sh, &base, &g[2], &b[2], &k[2], &l[2]) != VLP_OK) return 7;
+  for (int i = 0; i < 3; ++i) printf("%llu %llu %u\n", (unsigned long long)g[i], (unsigned long long)b[i], l[i]);
+  printf("%zu %zu\n", bytes[0], bytes[1]);
+  return 0;
+}
+"""
+
+
+def test_shape_struct_has_the_boundary_layout(tmp_path):
+    """A C caller that knows only the five-field vlp_shape gets the default
+    (optimized) circuits; vlp_circuit picks others through the _ex calls."""
+    import subprocess
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests", "capi"))
+    import capi_build as B
+    why = B.missing()
+    if why:
+        pytest.skip(why)
+    src = tmp_path / "shape_abi.c"
+    src.write_text(SHAPE_C)
+    exe = str(tmp_path / "shape_abi")
+    cmd = ["gcc", "-std=c11", "-O1", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+           "-L", B.PKG, "-lvlp", "-Wl,-rpath," + B.PKG, "-Wl,-rpath," + os.path.join(B.ROCM, "lib"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    rows = [tuple(int(v) for v in line.split()) for line in r.stdout.split("\n") if line.strip()]
+    default, opt, base, (b0, b1) = rows[0], rows[1], rows[2], rows[3]
+    assert default == opt and b0 == b1
+    g, br, depth = _oracle_counts("idm", 9, 16, 9, 1, True)
+    assert default == (g, br, depth)
+    g, br, depth = _oracle_counts("idm", 9, 16, 9, 1, False)
+    assert base == (g, br, depth) and base != opt
