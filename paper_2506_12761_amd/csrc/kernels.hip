@@ -457,7 +457,8 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
         const uint32_t s = (r * 64 + lane + 2048u - ab) & 2047u;
         D[r] = ((s >= 1024u ? 0u - src[r] : src[r]) - D[r] + DEC_OFFSET) ^ DIGIT_FLIP;
       }
-#pragma unroll 1
+      // Unrolled as in br2_rotate (5.5% less time per launch than a loop).
+#pragma unroll
       for (int lev = 0; lev < ELL; ++lev) {
         const g_u32* k0 = (const g_u32*)(bk_i + (size_t)((H * ELL + lev) * 4 + PR) * RING_N);
         uint32_t b0[16], b1[16];

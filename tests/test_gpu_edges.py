@@ -125,6 +125,37 @@ def test_evaluate_extreme_shapes(gpu, oracle_keys, mode, M, l, lS, d):
         assert np.array_equal(O.decrypt(oracle_keys, ctx.to_host(R)), P["R"])
 
 
+def test_circuit_argument_of_the_ex_calls(gpu, oracle_keys):
+    """The plain calls, given only the five-field shape, evaluate the
+    optimized circuits, as the _ex calls do with a NULL circuit or {1, 0};
+    {0, 0} gives the baseline chains' words; a bad agg_k is an argument error."""
+    vlp, ctx, ks = gpu
+    mode, M, l, lS, d = "idm", 3, 5, 2, 1
+    P = W.plain_workload(mode, M, l, lS, d, seed=77)
+    enc = W.encrypt_workload(oracle_keys, P, seed=78)
+    q, loc, pay = ctx.tensor(enc["query"]), ctx.tensor(enc["db_loc"]), ctx.tensor(enc["db_pay"])
+    shape = vlp.vlp_shape(vlp.MODES[mode], M, l, lS, d)
+    want = {True: W.oracle_outputs(oracle_keys, P, enc, optimized=True),
+            False: W.oracle_outputs(oracle_keys, P, enc, optimized=False)}
+    runs = [(lambda R, v: vlp.vlp_evaluate(ctx.ctx, ks, shape, q, loc, pay, R, v), True),
+            (lambda R, v: vlp.vlp_evaluate_ex(ctx.ctx, ks, shape, None, q, loc, pay, R, v), True),
+            (lambda R, v: vlp.vlp_evaluate_ex(ctx.ctx, ks, shape, vlp.vlp_circuit(1, 0), q, loc, pay, R, v), True),
+            (lambda R, v: vlp.vlp_evaluate_ex(ctx.ctx, ks, shape, vlp.vlp_circuit(0, 0), q, loc, pay, R, v), False)]
+    for run, opt in runs:
+        R, v = ctx.empty(lS, O.n + 1), ctx.empty(M, O.n + 1)
+        run(R, v)
+        ctx.sync()
+        v_want, R_want = want[opt]
+        assert np.array_equal(ctx.to_host(v), v_want) and np.array_equal(ctx.to_host(R), R_want), opt
+    R, v = ctx.empty(lS, O.n + 1), ctx.empty(M, O.n + 1)
+    with pytest.raises(vlp.VlpError) as e:
+        vlp.vlp_evaluate_ex(ctx.ctx, ks, shape, vlp.vlp_circuit(1, 1), q, loc, pay, R, v)
+    assert e.value.status == vlp.VLP_EINVAL
+    pr = vlp.vlp_program_create(ctx.ctx, ks, shape, q, loc, pay, R, v)
+    assert vlp.vlp_program_counts(ctx.ctx, pr)["blind_rotations"] == vlp.vlp_plan_counts(shape)["blind_rotations"]
+    vlp.vlp_program_destroy(ctx.ctx, pr)
+
+
 def test_step_rejects_a_program_listed_twice(gpu, oracle_keys):
     """A duplicated handle is an argument error that enqueues nothing; the
     programs then step to the oracle's words, and a program part-way through
