@@ -367,21 +367,63 @@ __device__ __forceinline__ void inv_stage1(uint32_t (&x)[16], const uint2* tws, 
   }
 }
 
-// tws: this prime's permuted LDS plane (stages 4..9).
+// Twiddle of butterfly k of forward stage S >= 4 (layout LAY, register bit
+// RB) in this prime's permuted LDS plane tws.
+template <int S, int (*LAY)(int, int), int RB>
+__device__ __forceinline__ uint2 fwd_tw(const uint2* tws, int lane, int k) {
+  return tws[(1 << S) + tw_perm(S, LAY(lane, bfly_reg<RB>(k)) >> (10 - S))];
+}
+// Forward transform, single prime; tws: this prime's permuted LDS plane
+// (stages 4..9).  A wavefront's LDS reads return in issue order, so a
+// twiddle read issued behind the transpose's reads comes back after all of
+// them and holds up stage 4, which could otherwise start on each register
+// pair as it arrives.  The twiddles of stages 4 and 5 are read before the
+// transpose, those of stage 6 right behind it (needed only after stages 4
+// and 5), those of stages 8 and 9 before the lane swaps of the Y -> Z move;
+// stage 7 reads its own.  Per lane, stages 4..9 use 1, 2, 4, 8, 4, 8
+// distinct twiddles: butterfly k of stage 5 shares with k & 4, of stage 6
+// with k & 6, of stage 8 with k & 3.  (11.37 -> 10.85-10.97 ms per launch of
+// the blind rotation against every stage reading its own.)
 template <int PR>
 __device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws, int lane) {
+  constexpr uint32_t P = Prime<PR>::P;
+  const uint2 t4 = fwd_tw<4, lay_y, 3>(tws, lane, 0);
+  const uint2 t5a = fwd_tw<5, lay_y, 2>(tws, lane, 0), t5b = fwd_tw<5, lay_y, 2>(tws, lane, 4);
   fwd_stage1<PR, 0, lay_a, 3>(x, tws, lane);
   fwd_stage1<PR, 1, lay_a, 2>(x, tws, lane);
   fwd_stage1<PR, 2, lay_a, 1>(x, tws, lane);
   fwd_stage1<PR, 3, lay_a, 0>(x, tws, lane);
   transpose_a_to_y(x, buf, lane);
-  fwd_stage1<PR, 4, lay_y, 3>(x, tws, lane);
-  fwd_stage1<PR, 5, lay_y, 2>(x, tws, lane);
-  fwd_stage1<PR, 6, lay_y, 1>(x, tws, lane);
+  uint2 t6[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t6[k] = fwd_tw<6, lay_y, 1>(tws, lane, 2 * k);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) bfly_ct(x[k], x[k | 8], t4.x, t4.y, P);  // stage 4 (register bit 3)
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // stage 5 (register bit 2)
+    const int r = bfly_reg<2>(k);
+    const uint2 w = r < 8 ? t5a : t5b;
+    bfly_ct(x[r], x[r | 4], w.x, w.y, P);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // stage 6 (register bit 1)
+    const int r = bfly_reg<1>(k);
+    bfly_ct(x[r], x[r | 2], t6[k >> 1].x, t6[k >> 1].y, P);
+  }
   fwd_stage1<PR, 7, lay_y, 0>(x, tws, lane);
+  uint2 t8[4], t9[8];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t8[k] = fwd_tw<8, lay_z, 3>(tws, lane, k);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t9[k] = fwd_tw<9, lay_z, 2>(tws, lane, k);
   swap_yz(x);  // layout Y -> Z
-  fwd_stage1<PR, 8, lay_z, 3>(x, tws, lane);
-  fwd_stage1<PR, 9, lay_z, 2>(x, tws, lane);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) bfly_ct(x[k], x[k | 8], t8[k & 3].x, t8[k & 3].y, P);  // stage 8 (register bit 3)
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // stage 9 (register bit 2)
+    const int r = bfly_reg<2>(k);
+    bfly_ct(x[r], x[r | 4], t9[k].x, t9[k].y, P);
+  }
 }
 
 template <int PR>
