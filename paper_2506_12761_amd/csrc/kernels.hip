@@ -486,6 +486,10 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
       xbuf[r * 64 + lane] = redc_s(H ? m0[r] : m1[r], P, PINV);  // (-2P, 2P)
       x[r] = redc_s(H ? m1[r] : m0[r], P, PINV);
     }
+    // The first two inverse stages' twiddles, read before the partner's
+    // products so that they are not queued behind those reads.
+    InvTw98 itw;
+    inv_tw98_load(itw, tws, lane);
     __syncthreads();  // B1
     uint32_t oth[16];
 #pragma unroll
@@ -493,7 +497,7 @@ __device__ __forceinline__ void br4_rotate(const BrItem& I, uint32_t* acc, const
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] += oth[r];  // (-4P, 4P)
-    ntt_inv1<PR>(x, buf, tws, lane);
+    ntt_inv1<PR>(x, itw, buf, tws, lane);
     // Wave (0, H) lifts registers 0..7, wave (1, H) registers 8..15: each parks
     // the half the other one lifts.
     wave_lds_sync();  // the transform's last reads of buf are done

@@ -426,6 +426,50 @@ __device__ __forceinline__ void ntt_fwd1(uint32_t (&x)[16], uint32_t* buf, const
   }
 }
 
+// Twiddle of butterfly k of inverse stage S >= 4 (layout LAY, register bit
+// RB) in this prime's permuted LDS plane tws.
+template <int S, int (*LAY)(int, int), int RB>
+__device__ __forceinline__ uint2 inv_tw(const uint2* tws, int lane, int k) {
+  return tws[(1 << S) + tw_perm(S, (1 << S) - 1 - (LAY(lane, bfly_reg<RB>(k)) >> (10 - S)))];
+}
+// The twiddles of inverse stages 9 (eight per lane) and 8 (four: butterfly k
+// shares with k & 3), for a caller that reads them ahead of other LDS reads
+// the first stages must not wait behind.
+struct InvTw98 {
+  uint2 s9[8], s8[4];
+};
+__device__ __forceinline__ void inv_tw98_load(InvTw98& w, const uint2* tws, int lane) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w.s9[k] = inv_tw<9, lay_z, 2>(tws, lane, k);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w.s8[k] = inv_tw<8, lay_z, 3>(tws, lane, k);
+}
+
+// Inverse transform whose stages 9 and 8 take the twiddles read by inv_tw98_load.
+template <int PR>
+__device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], const InvTw98& w, uint32_t* buf, const uint2* tws,
+                                         int lane) {
+  constexpr uint32_t P = Prime<PR>::P;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // stage 9 (register bit 2)
+    const int r = bfly_reg<2>(k);
+    bfly_gs_neg<inv_bound(9), inv_reduces(9)>(x[r], x[r | 4], w.s9[k].x, w.s9[k].y, P);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)  // stage 8 (register bit 3)
+    bfly_gs_neg<inv_bound(8), inv_reduces(8)>(x[k], x[k | 8], w.s8[k & 3].x, w.s8[k & 3].y, P);
+  swap_yz(x);  // layout Z -> Y
+  inv_stage1<PR, 7, lay_y, 0>(x, tws, lane);
+  inv_stage1<PR, 6, lay_y, 1>(x, tws, lane);
+  inv_stage1<PR, 5, lay_y, 2>(x, tws, lane);
+  inv_stage1<PR, 4, lay_y, 3>(x, tws, lane);
+  transpose_y_to_a(x, buf, lane);
+  inv_stage1<PR, 3, lay_a, 0>(x, tws, lane);
+  inv_stage1<PR, 2, lay_a, 1>(x, tws, lane);
+  inv_stage1<PR, 1, lay_a, 2>(x, tws, lane);
+  inv_stage1<PR, 0, lay_a, 3>(x, tws, lane);
+}
+
 template <int PR>
 __device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws, int lane) {
   inv_stage1<PR, 9, lay_z, 2>(x, tws, lane);
