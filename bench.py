@@ -51,7 +51,7 @@ PEAK_MODMUL = VALU_LANE_OPS / (OPS_PER_RESIDUE_BUTTERFLY * RESIDUES_PER_MODMUL) 
 # workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE;
 # copy-calibrated), valid only for the kernel sources it was measured on
 # (their sha256 prefix) and the launch shape it was measured with.
-TRAFFIC_MEASURED = {"kernel_sha": "74245949ea95a4bc", "bytes_per_launch": 5.16355e+08,
+TRAFFIC_MEASURED = {"kernel_sha": "749f0fca55ff871c", "bytes_per_launch": 5.16355e+08,
                     "launch": {"br_waves_per_rotation": 0, "br_rotations_per_block": 4, "br_blocks_per_cu": 1,
                                "ks_gates_per_block": 512}}
 KERNEL_SOURCES = ("kernels.hip", "wave_ntt.h", "rns.h", "vlp_api.cpp")

@@ -445,7 +445,8 @@ __device__ __forceinline__ void inv_tw98_load(InvTw98& w, const uint2* tws, int 
   for (int k = 0; k < 4; ++k) w.s8[k] = inv_tw<8, lay_z, 3>(tws, lane, k);
 }
 
-// Inverse transform whose stages 9 and 8 take the twiddles read by inv_tw98_load.
+// Inverse transform, single prime (layout Z, |values| < 4P -> layout A, |values|
+// < 16P), whose stages 9 and 8 take the twiddles read by inv_tw98_load.
 template <int PR>
 __device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], const InvTw98& w, uint32_t* buf, const uint2* tws,
                                          int lane) {
@@ -458,22 +459,6 @@ __device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], const InvTw98& w, ui
 #pragma unroll
   for (int k = 0; k < 8; ++k)  // stage 8 (register bit 3)
     bfly_gs_neg<inv_bound(8), inv_reduces(8)>(x[k], x[k | 8], w.s8[k & 3].x, w.s8[k & 3].y, P);
-  swap_yz(x);  // layout Z -> Y
-  inv_stage1<PR, 7, lay_y, 0>(x, tws, lane);
-  inv_stage1<PR, 6, lay_y, 1>(x, tws, lane);
-  inv_stage1<PR, 5, lay_y, 2>(x, tws, lane);
-  inv_stage1<PR, 4, lay_y, 3>(x, tws, lane);
-  transpose_y_to_a(x, buf, lane);
-  inv_stage1<PR, 3, lay_a, 0>(x, tws, lane);
-  inv_stage1<PR, 2, lay_a, 1>(x, tws, lane);
-  inv_stage1<PR, 1, lay_a, 2>(x, tws, lane);
-  inv_stage1<PR, 0, lay_a, 3>(x, tws, lane);
-}
-
-template <int PR>
-__device__ __forceinline__ void ntt_inv1(uint32_t (&x)[16], uint32_t* buf, const uint2* tws, int lane) {
-  inv_stage1<PR, 9, lay_z, 2>(x, tws, lane);
-  inv_stage1<PR, 8, lay_z, 3>(x, tws, lane);
   swap_yz(x);  // layout Z -> Y
   inv_stage1<PR, 7, lay_y, 0>(x, tws, lane);
   inv_stage1<PR, 6, lay_y, 1>(x, tws, lane);
