@@ -121,3 +121,23 @@ def test_alone_equals_mixed():
             assert np.array_equal(R_m, R_a) and np.array_equal(v_m, v_a), r.rid
             assert np.array_equal(O.decrypt(keys[r.client], v_m), P["v"])
             assert np.array_equal(O.decrypt(keys[r.client], R_m), P["R"])
+
+
+def test_alone_equals_mixed_at_larger_sizes():
+    """Three queries of 64-200 records (all three modes, two clients) through
+    the serving loop with the shortest-remaining-work policy and a small
+    per-step cap: every result word equals the query run alone, and v and R
+    decrypt to the plaintext answers."""
+    from paper_2506_12761_amd import vlp
+    keys = {0: O.keygen(synth.key_randomness(0x5EED0103)), 1: O.keygen(synth.key_randomness(0x5EED0104))}
+    specs = [(0, "idm", 200, 8, 4, 1, 0.0), (1, "cov", 100, 6, 3, 2, 0.0), (0, "intv", 64, 8, 2, 2, 0.0)]
+    with vlp.Context(0) as ctx:
+        ks, reqs, plain = _setup(ctx, keys, specs)
+        alone = _alone(ctx, ks, reqs)
+        st = serve(reqs, GpuExecutor(ctx, ks), policy="srpt", step_cap=2048)
+        assert st["queries"] == len(reqs) and st["max_active"] >= 2
+        for r, (R_a, v_a), P in zip(reqs, alone, plain):
+            R_m, v_m = ctx.to_host(r.payload["R"]), ctx.to_host(r.payload["v"])
+            assert np.array_equal(R_m, R_a) and np.array_equal(v_m, v_a), r.rid
+            assert np.array_equal(O.decrypt(keys[r.client], v_m), P["v"])
+            assert np.array_equal(O.decrypt(keys[r.client], R_m), P["R"])
